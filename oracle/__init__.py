@@ -1,0 +1,263 @@
+"""Python handle on the FP64 CPU oracle (``fireoracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke``
+and by the benchmark's CPU-baseline leg, never by the product package.  It
+shares no code with the GPU path; both only consume the arrays produced by
+the ``synth`` generators.
+
+Scenario objects are duck-typed: anything with ``H, W, cell_m, seed,
+scenario_id, p_veg, p_den, elevation, wind_speed, wind_dir,
+wind_speed_scalar, wind_dir_scalar, init_burning`` and the parameters
+``p_h, a, c1, c2, p_continue`` works.  FP32 inputs and FP32 parameter values
+are widened to double before any arithmetic.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+# FP32 rounding of the f_p constant 1.1486328125 (Eq. 5 / 8).
+C_F32 = float(np.float32(1.1486328125))
+
+
+def build(force: bool = True) -> str:
+    """Compile ``fireoracle.c`` into ``liboracle.so`` (gcc, FP64, no fast-math)."""
+    src = os.path.join(_HERE, "fireoracle.c")
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+        ("cell_m", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("scenario", ctypes.c_uint32),
+        ("p_h", ctypes.c_double), ("a", ctypes.c_double),
+        ("c1", ctypes.c_double), ("c2", ctypes.c_double),
+        ("p_continue", ctypes.c_double),
+        ("c", ctypes.c_double),
+        ("p_veg", ctypes.c_void_p), ("p_den", ctypes.c_void_p), ("elev", ctypes.c_void_p),
+        ("wind_speed", ctypes.c_void_p), ("wind_dir", ctypes.c_void_p),
+        ("wind_speed_scalar", ctypes.c_double), ("wind_dir_scalar", ctypes.c_double),
+    ]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build(force=False)
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER(_Problem)
+    vp = ctypes.c_void_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    lib.fo_philox4x32_10.argtypes = [vp, vp, vp]
+    lib.fo_draws.argtypes = [P, i32, i64, vp, vp]
+    lib.fo_edge_q.argtypes = [P, i32, i32, i32, i32, vp, vp]
+    lib.fo_edge_q.restype = dbl
+    lib.fo_pignite_cell.argtypes = [P, vp, i32, i32]
+    lib.fo_pignite_cell.restype = dbl
+    lib.fo_pignite_map.argtypes = [P, vp, vp]
+    lib.fo_dpignite_cell.argtypes = [P, vp, i32, i32, vp]
+    lib.fo_step.argtypes = [P, i32, vp, vp, vp, vp, dbl, vp]
+    lib.fo_step.restype = i64
+    lib.fo_run.argtypes = [P, i32, i32, vp, vp, vp, dbl]
+    lib.fo_run.restype = i64
+    lib.fo_loss.argtypes = [i32, i32, vp, vp, i32, vp]
+    lib.fo_loss.restype = dbl
+    lib.fo_grad.argtypes = [P, i32, vp, vp, vp]
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class Problem:
+    """A scenario frozen into the oracle's C struct (keeps its arrays alive)."""
+
+    def __init__(self, scn, c=C_F32, **override):
+        self.H, self.W = int(scn.H), int(scn.W)
+        f = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float32)
+        self.p_veg, self.p_den = f(scn.p_veg), f(scn.p_den)
+        self.elev = f(scn.elevation)
+        self.ws, self.wd = f(scn.wind_speed), f(scn.wind_dir)
+        par = {k: float(np.float32(getattr(scn, k)))
+               for k in ("p_h", "a", "c1", "c2", "p_continue")}
+        par.update({k: float(v) for k, v in override.items()
+                    if k in ("p_h", "a", "c1", "c2", "p_continue")})
+        self.params = par
+        self.seed = int(override.get("seed", scn.seed))
+        self.scenario = int(override.get("scenario_id", scn.scenario_id))
+        self.s = _Problem(self.H, self.W, float(scn.cell_m), self.seed, self.scenario,
+                          par["p_h"], par["a"], par["c1"], par["c2"], par["p_continue"],
+                          float(c), _ptr(self.p_veg), _ptr(self.p_den), _ptr(self.elev),
+                          _ptr(self.ws), _ptr(self.wd),
+                          float(np.float32(scn.wind_speed_scalar)),
+                          float(np.float32(scn.wind_dir_scalar)))
+        self.init_burning = np.ascontiguousarray(scn.init_burning, dtype=np.uint8)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def _problem(scn, **kw):
+    return scn if isinstance(scn, Problem) else Problem(scn, **kw)
+
+
+def philox4x32_10(ctr, key):
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib.fo_philox4x32_10(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+def draws(scn, t, cell):
+    lib = _load()
+    pb = _problem(scn)
+    ui, uc = ctypes.c_double(), ctypes.c_double()
+    lib.fo_draws(pb.ref, int(t), int(cell), ctypes.byref(ui), ctypes.byref(uc))
+    return ui.value, uc.value
+
+
+def edge_q(scn, r, c, dr, dc, **kw):
+    """(q, theta_s in degrees, cos(delta)) of the edge (r+dr, c+dc) -> (r, c)."""
+    lib = _load()
+    pb = _problem(scn, **kw)
+    th, cd = ctypes.c_double(), ctypes.c_double()
+    q = lib.fo_edge_q(pb.ref, r, c, dr, dc, ctypes.byref(th), ctypes.byref(cd))
+    return q, th.value, cd.value
+
+
+def initial_state(scn):
+    return (np.asarray(scn.init_burning) != 0).astype(np.uint8)
+
+
+def pignite_map(scn, S, **kw):
+    lib = _load()
+    pb = _problem(scn, **kw)
+    S = np.ascontiguousarray(S, dtype=np.uint8)
+    out = np.zeros((pb.H, pb.W), dtype=np.float64)
+    lib.fo_pignite_map(pb.ref, S.ctypes.data, out.ctypes.data)
+    return out
+
+
+def pignite_cell(scn, S, r, c, **kw):
+    lib = _load()
+    pb = _problem(scn, **kw)
+    S = np.ascontiguousarray(S, dtype=np.uint8)
+    return lib.fo_pignite_cell(pb.ref, S.ctypes.data, r, c)
+
+
+def dpignite_cell(scn, S, r, c, **kw):
+    lib = _load()
+    pb = _problem(scn, **kw)
+    S = np.ascontiguousarray(S, dtype=np.uint8)
+    g = np.zeros(4, dtype=np.float64)
+    lib.fo_dpignite_cell(pb.ref, S.ctypes.data, r, c, g.ctypes.data)
+    return g
+
+
+def step(scn, t, S_prev, tie_eps=1e-5, yhat=None, **kw):
+    """One step: returns (S_next, tie mask, p_ignite map of S_prev, tie count)."""
+    lib = _load()
+    pb = _problem(scn, **kw)
+    S_prev = np.ascontiguousarray(S_prev, dtype=np.uint8)
+    nxt = np.zeros_like(S_prev)
+    tie = np.zeros_like(S_prev)
+    pmap = np.zeros(S_prev.shape, dtype=np.float64)
+    n = lib.fo_step(pb.ref, int(t), S_prev.ctypes.data, nxt.ctypes.data, _ptr(yhat),
+                    tie.ctypes.data, float(tie_eps), pmap.ctypes.data)
+    return nxt, tie.astype(bool), pmap, int(n)
+
+
+def run(scn, T, t0=0, S=None, tie_eps=1e-5, want_yhat=False, want_tstep=False, **kw):
+    """Steps t0+1..t0+T from S (default: the ignition state).
+
+    Returns dict(S=final state, ties=count, yhat=..., tstep=...).
+    ``yhat`` starts at 1 on initially burning cells (their accumulator value
+    is a constant) and 0 elsewhere; ``tstep`` is the ignition step (0 for
+    the initial cells, -1 for cells never ignited).
+    """
+    lib = _load()
+    pb = _problem(scn, **kw)
+    S = initial_state(scn) if S is None else np.array(S, dtype=np.uint8, copy=True)
+    S = np.ascontiguousarray(S)
+    yhat = None
+    if want_yhat:
+        yhat = (S == 1).astype(np.float64)
+    tstep = None
+    if want_tstep:
+        tstep = np.where(S == 1, 0, -1).astype(np.int32)
+    ties = lib.fo_run(pb.ref, int(t0), int(T), S.ctypes.data, _ptr(yhat), _ptr(tstep),
+                      float(tie_eps))
+    return {"S": S, "ties": int(ties), "yhat": yhat, "tstep": tstep}
+
+
+def loss(yhat, y, kind=0):
+    """Eq. 10 reading: returns (loss, dL/dyhat)."""
+    lib = _load()
+    yhat = np.ascontiguousarray(yhat, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.uint8)
+    H, W = yhat.shape
+    lam = np.zeros_like(yhat)
+    L = lib.fo_loss(H, W, yhat.ctypes.data, y.ctypes.data, int(kind), lam.ctypes.data)
+    return L, lam
+
+
+def grad(scn, T, lam, **kw):
+    """Analytic gradient of sum(lam * yhat) w.r.t. (p_h, a, c1, c2)."""
+    lib = _load()
+    pb = _problem(scn, **kw)
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    g = np.zeros(4, dtype=np.float64)
+    lib.fo_grad(pb.ref, int(T), pb.init_burning.ctypes.data, lam.ctypes.data,
+                g.ctypes.data)
+    return g
+
+
+PARAM_NAMES = ("p_h", "a", "c1", "c2")
+
+
+def fd_grad(scn, T, y, kind=0, h_rel=1e-7, h_min=1e-9):
+    """Central finite differences of L(yhat(theta)) with common random numbers.
+
+    Returns (g, flips): flips[k] counts cells whose ignition step differs
+    between the +h and -h runs for parameter k (0 means the discrete
+    trajectory was identical and the difference quotient is exact up to
+    O(h^2) and rounding).
+    """
+    base = {k: float(np.float32(getattr(scn, k))) for k in PARAM_NAMES}
+    g = np.zeros(4)
+    flips = np.zeros(4, dtype=np.int64)
+    for k, name in enumerate(PARAM_NAMES):
+        h = max(abs(base[name]) * h_rel, h_min)
+        outs = []
+        for sgn in (+1, -1):
+            ov = dict(base)
+            ov[name] = base[name] + sgn * h
+            r = run(scn, T, want_yhat=True, want_tstep=True, **ov)
+            outs.append(r)
+        Lp = loss(outs[0]["yhat"], y, kind)[0]
+        Lm = loss(outs[1]["yhat"], y, kind)[0]
+        g[k] = (Lp - Lm) / (2 * h)
+        flips[k] = int(np.count_nonzero(outs[0]["tstep"] != outs[1]["tstep"]))
+    return g, flips
