@@ -1,0 +1,282 @@
+#!/usr/bin/env python3
+"""Throughput of the wildfire cellular automaton on one MI355X.
+
+One benchmark step = one full forward run of the 4096 x 4096 workload
+(1000 time steps from a 20 x 20 ignition patch, lakes, per-cell wind, 30 m
+cells): reset to the ignition state, then every CA step (candidate
+detection, per-edge Eq. 1-5, Eq. 9, Philox draws, transition) on the GPU.
+Inputs are resident in HBM before the timed region.
+
+Side legs, reported in the same JSON line:
+  plain_step   the same grid advanced one step per launch with no tile
+               skipping (the straightforward stencil);
+  calibration  64 scenarios of 1024 x 1024, 200 steps, checkpoints every 20:
+               forward + Eq. 10 BCE loss + adjoint + AdamW, in grad-steps/s;
+  batched      256 scenarios with log-uniform sides 256-2048, 300 steps, one
+               launch sequence over all of them;
+  cpu_baseline the FP64 oracle on the host, on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--legs main,plain,calib,batched,cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/s (G cells·steps/s) + % HBM roofline; calibration grad-steps/s"
+HBM_PEAK_GBS = 8000.0
+# Bytes per cell-step of the dense formulation (every cell reads its 2-bit
+# state, F = (1+p_veg)(1+p_den), elevation, wind speed and direction, and
+# writes 2 bits): 0.5 + 4 + 4 + 8.
+DENSE_BYTES_PER_CELL_STEP = 16.5
+DEFAULT_EXEC = dict(tile_rows=16, tile_words=8, depth=8, skip=True)
+PLAIN_EXEC = dict(tile_rows=16, tile_words=8, depth=1, skip=False)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "api.hip", "internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2502_18738_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(name):
+    """Per-launch HBM bytes from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return d
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ev0.elapsed_time(ev1) / 1e3
+
+
+def leg_main(args, torch, Sim, synth):
+    s = synth.config2()
+    T = s.T
+    sim = Sim([s], exec=DEFAULT_EXEC)
+    launches_per_run = -(-T // DEFAULT_EXEC["depth"])
+
+    def run():
+        sim.reset()
+        sim.run(T)
+
+    wall, gpu = timed(run, args.steps, args.warmup, torch)
+    cells = s.H * s.W
+    rate = cells * T * args.steps / wall / 1e9
+    # dominant kernel: the temporally blocked step; all GPU time of the timed
+    # region is charged to its launches (reset kernels are included, so the
+    # per-launch duration is an upper bound)
+    launch_s = gpu / (args.steps * launches_per_run)
+    unit_cells = cells * DEFAULT_EXEC["depth"]
+    achieved = DENSE_BYTES_PER_CELL_STEP * unit_cells / launch_s / 1e9
+    roof = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 3), "traffic": None,
+        "kernel": "k_step<16,8,8,false>", "launch_us": round(launch_s * 1e6, 2),
+        "basis": "effective: dense-formulation bytes (16.5 B per cell-step) x cell-steps "
+                 "per launch; the kernel reads fields only for cells with a trial",
+    }
+    tr = load_traffic("k_step_config2")
+    if tr:
+        roof["traffic"] = tr["bytes_per_launch"]
+        roof["traffic_GBps"] = round(tr["bytes_per_launch"] / launch_s / 1e9, 1)
+    # work actually done: tiles processed and trials (separate counting run)
+    st = Sim([s], exec=DEFAULT_EXEC, stats=True)
+    st.run(T)
+    torch.cuda.synchronize()
+    cnt = st.stats()
+    del st
+    out = {
+        "value": round(rate, 3),
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "gpu_ms_per_step": round(gpu / args.steps * 1e3, 3),
+        "roofline": roof,
+        "work": {"tiles_processed_per_run": cnt["tiles"], "trials_per_run": cnt["trials"],
+                 "near_ties_per_run": cnt["ties"], "launches_per_run": cnt["launches"],
+                 "tiles_per_launch_if_dense": sim_tiles(s, DEFAULT_EXEC)},
+        "config": {"workload": "4096x4096 grid, 1000 steps, 10% lakes, per-cell wind, "
+                               "elevation 0-1500 m, 20x20 ignition patch, 30 m cells",
+                   "H": s.H, "W": s.W, "T": T, "scenarios": 1, "exec": DEFAULT_EXEC},
+    }
+    return out, s
+
+
+def sim_tiles(s, ex):
+    pitch = -(-s.W // 32)
+    return (-(-s.H // ex["tile_rows"])) * (-(-pitch // ex["tile_words"]))
+
+
+def leg_plain(args, torch, Sim, s):
+    """One step per launch, every tile processed (no skipping, no blocking)."""
+    T = 200
+    sim = Sim([s], exec=PLAIN_EXEC)
+
+    def run():
+        sim.reset()
+        sim.run(T)
+
+    wall, gpu = timed(run, 1, 1, torch)
+    cells = s.H * s.W
+    launch_s = gpu / T
+    return {
+        "exec": PLAIN_EXEC, "steps": T,
+        "G_cell_steps_per_s": round(cells * T / wall / 1e9, 3),
+        "launch_us": round(launch_s * 1e6, 2),
+        "effective_dense_GBps": round(DENSE_BYTES_PER_CELL_STEP * cells / launch_s / 1e9, 1),
+    }
+
+
+def leg_calib(args, torch, Sim, synth):
+    n, T, ck = 64, 200, 20
+    log("calibration: generating", n, "scenarios")
+    cases = [synth.config4_scenario(b) for b in range(n)]
+    true_s = [c[0] for c in cases]
+    gen = Sim(true_s)
+    gen.run(T)
+    target = torch.cat([(gen.get_state(b).sum(0) != 0).to(torch.uint8).view(-1)
+                        for b in range(n)])
+    del gen
+    start = [c[1] for c in cases]
+    sim = Sim(true_s, calib=True, T_max=T, ckpt_every=ck, exec=DEFAULT_EXEC)
+    theta = torch.tensor(start, dtype=torch.float32, device="cuda", requires_grad=True)
+    opt = torch.optim.AdamW([theta], lr=5e-3)
+    pc = torch.tensor([s.p_continue for s in true_s], dtype=torch.float32)
+    lo = torch.tensor([0.2, 0.0, 0.0, 0.0], device="cuda")
+    hi = torch.tensor([1.0, 1.0, 1.0, 1.0], device="cuda")
+    step = [0]
+
+    def grad_step():
+        p = theta.detach().cpu()
+        sim.set_params(torch.cat([p, pc[:, None]], 1).tolist())
+        sim.reset([1000 + step[0]] * n)
+        sim.run(T)
+        loss, g = sim.loss_grad(target, 0)
+        theta.grad = g.to(torch.float32)
+        opt.step()
+        with torch.no_grad():
+            theta.copy_(torch.maximum(torch.minimum(theta, hi), lo))
+        step[0] += 1
+        return loss
+
+    K = max(2, args.steps)
+    wall, gpu = timed(grad_step, K, 1, torch)
+    cells = 1024 * 1024 * n
+    return {
+        "metric": "calibration grad-steps/s", "value": round(K / wall, 3),
+        "ms_per_grad_step": round(wall / K * 1e3, 2),
+        "G_cell_steps_per_s": round(2 * cells * T * K / wall / 1e9, 3),
+        "config": {"workload": "64 scenarios 1024x1024, 200 steps, checkpoints every 20, "
+                               "BCE loss, AdamW lr 5e-3 with clamps",
+                   "exec": DEFAULT_EXEC},
+    }
+
+
+def leg_batched(args, torch, Sim, synth):
+    n, T = 256, 300
+    log("batched: generating", n, "scenarios")
+    scs = [synth.config3_scenario(b, T=T) for b in range(n)]
+    ex = dict(tile_rows=16, tile_words=8, depth=8, skip=True)
+    sim = Sim(scs, exec=ex)
+
+    def run():
+        sim.reset()
+        sim.run(T)
+
+    wall, gpu = timed(run, 1, 1, torch)
+    cells = sum(s.H * s.W for s in scs)
+    return {
+        "value": round(cells * T / wall / 1e9, 3), "unit": "G cell-steps/s",
+        "ms_per_run": round(wall * 1e3, 2), "cells": cells,
+        "config": {"workload": "256 scenarios, sides log-uniform 256-2048, 300 steps, "
+                               "+-20% parameter jitter", "exec": ex},
+    }
+
+
+def leg_cpu(args, s):
+    import oracle
+    steps = 40
+    t0 = time.perf_counter()
+    oracle.run(s, steps)
+    dt = time.perf_counter() - t0
+    return {"value": round(s.H * s.W * steps / dt / 1e9, 5), "unit": "G cell-steps/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{s.H}x{s.W} grid of the main workload, steps 1-{steps} from the "
+                      "ignition patch, FP64 C loop, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--legs", default="main,plain,calib,batched,cpu")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "decomposition is not built", file=sys.stderr)
+        sys.exit(2)
+    legs = set(args.legs.split(","))
+
+    import torch
+    import synth
+    from paper_2502_18738_amd.sim import Sim
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+
+    log("main: config 2")
+    main_out, s2 = leg_main(args, torch, Sim, synth)
+    res = {
+        "metric": METRIC, "value": main_out["value"], "unit": "G cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_out["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": main_out["config"], "roofline": main_out["roofline"],
+        "gpu_ms_per_step": main_out["gpu_ms_per_step"], "work": main_out["work"],
+    }
+    if "plain" in legs:
+        log("plain step")
+        res["plain_step"] = leg_plain(args, torch, Sim, s2)
+    if "calib" in legs:
+        res["calibration"] = leg_calib(args, torch, Sim, synth)
+    if "batched" in legs:
+        res["batched"] = leg_batched(args, torch, Sim, synth)
+    if "cpu" in legs:
+        log("cpu baseline")
+        res["cpu_baseline"] = leg_cpu(args, s2)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

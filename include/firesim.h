@@ -1,0 +1,205 @@
+/*
+ * firesim.h -- C ABI of the MI355X (gfx950) wildfire cellular-automaton library.
+ *
+ * The library advances the stochastic cellular automaton of "PyTorchFire: A
+ * GPU-Accelerated Wildfire Simulator with Differentiable Cellular Automata"
+ * (Xia & Cheng, Environmental Modelling & Software 188, 2025) on the GPU:
+ *   - inputs, parameters and outputs as listed in Sec. 2.1;
+ *   - per-edge propagation probability, Eq. 1-5 (slope from elevation, wind,
+ *     fuel, f_p(x) = tanh(c x) with c = 1.1486328125 rounded to FP32);
+ *   - ignition probability over the Moore neighbourhood, Eq. 9;
+ *   - the transition rules of Sec. 2.2 (burnable -> burning w.p. p_ignite when
+ *     a neighbour burns, burning stays burning w.p. p_continue, burned is
+ *     absorbing), all decided from the state at t-1;
+ *   - the accumulator of p_ignite at the ignition step (Sec. 2.2, data flow)
+ *     and the gradient of the Eq. 10 loss through it (Sec. 2.3).
+ *
+ * Conventions shared by every call
+ *   - Grids are row-major H x W, row 0 = north, columns run east.  Wind
+ *     direction is the heading the wind blows toward, degrees counter-
+ *     clockwise from east.  Cells outside the grid never burn.
+ *   - Random numbers: Philox4x32-10 with key = seed and counter
+ *     (cell, 0, step, scenario_id), cell = r*W + c, step = index of the state
+ *     being produced (1 for the first step).  Word 0 gives the ignition draw,
+ *     word 1 the continue draw, each (w >> 8) * 2^-24.  A cell ignites iff
+ *     draw < p_ignite (FP32); it keeps burning iff draw < p_continue.
+ *   - Ownership: every pointer in sim_fields, every output buffer and the
+ *     workspace are DEVICE pointers owned by the caller.  They must stay valid
+ *     until sim_destroy.  The library never allocates device memory.
+ *   - Streams: all work is enqueued on the stream given to sim_init; calls
+ *     return once the work is enqueued (sim_init also waits for its
+ *     validation result).  Results are valid after the stream synchronises.
+ *   - Errors: every int-returning call returns SIM_OK (0) or a negative
+ *     SIM_E_* code and records a message readable with sim_last_error.
+ *     Argument checks run before any GPU work, so a rejected call has no
+ *     effect.  No C++ exception crosses this boundary.
+ *   - Thread safety: a handle must not be used from two threads at once.
+ */
+#ifndef FIRESIM_H
+#define FIRESIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Exported entry points (the library is built with hidden visibility). */
+#if defined(__GNUC__) || defined(__clang__)
+#define SIM_API __attribute__((visibility("default")))
+#else
+#define SIM_API
+#endif
+
+#define SIM_OK 0
+#define SIM_E_ARG (-1)        /* null / misaligned pointer, bad enum value   */
+#define SIM_E_SHAPE (-2)      /* H, W, n, T, tile or depth out of range      */
+#define SIM_E_PARAM (-3)      /* non-finite or out-of-range parameter/field  */
+#define SIM_E_WORKSPACE (-4)  /* workspace too small or misaligned           */
+#define SIM_E_HIP (-5)        /* a HIP runtime call failed                   */
+#define SIM_E_STATE (-6)      /* call not valid in the handle's state        */
+
+/* sim_init flags */
+#define SIM_F_CALIB 1u        /* keep the accumulator and state checkpoints   */
+#define SIM_F_STATS 2u        /* count processed tiles, trials and near ties  */
+
+/* loss kinds of sim_loss_grad (Eq. 10) */
+#define SIM_LOSS_BCE 0        /* BCE-with-logits over the bounding-box crop   */
+#define SIM_LOSS_BCE_MSE 1    /* BCE + MSE of 4x4, stride-4 average pools     */
+#define SIM_LOSS_MSE 2        /* MSE term only                                */
+
+typedef struct sim_handle sim_handle;
+
+/* The five parameters of Sec. 2.1 (p_continue is never differentiated). */
+typedef struct {
+    float p_h, a, c1, c2, p_continue;
+} sim_params;
+
+/* Input fields of one scenario (Sec. 2.1).  Device pointers, FP32, H*W,
+ * row-major, caller-owned.  p_veg = -1 (or p_den = -1) marks a cell without
+ * fuel (Sec. 2.2: a small enough p_veg gives zero propagation); values below
+ * -1 are rejected.  Slope is derived from the elevation with Eq. 1 in place of
+ * the paper's H x W x 3 x 3 slope tensor.  wind_speed / wind_dir_deg may be
+ * NULL, in which case the two scalars apply to every cell. */
+typedef struct {
+    const float* p_veg;
+    const float* p_den;
+    const float* elevation_m;
+    const float* wind_speed;
+    const float* wind_dir_deg;
+    float wind_speed_scalar;
+    float wind_dir_deg_scalar;
+    const uint8_t* init_burning;   /* H*W bytes, non-zero = burning at t = 0 */
+} sim_fields;
+
+/* One scenario.  cell_m is l of Eq. 1 in metres; seed keys the Philox stream;
+ * scenario_id is the fourth counter word (distinct ids give independent
+ * streams under one seed). */
+typedef struct {
+    int32_t H, W;
+    float cell_m;
+    uint32_t scenario_id;
+    uint64_t seed;
+    sim_params params;
+    sim_fields f;
+} sim_desc;
+
+/* Execution shape: rows x words of one tile (a word is 32 cells), steps per
+ * launch (temporal block depth, 1 <= depth <= tile_rows and <= 32), and
+ * whether tiles with no burning cell within reach are skipped.  Every shape
+ * produces bit-identical states. */
+typedef struct {
+    int32_t tile_rows, tile_words, depth, skip;
+} sim_exec;
+
+/* Bytes of workspace sim_init needs for these scenarios.  ckpt_every and
+ * T_max size the checkpoint store and are only used with SIM_F_CALIB.
+ * Returns 0 when the arguments are invalid. */
+SIM_API size_t sim_workspace_size(const sim_desc* descs, int32_t n, uint32_t flags,
+                          int32_t ckpt_every, int32_t T_max);
+
+/* Create a handle over n scenarios.  `descs` is a host array of n entries.
+ * Validates every field on the device (p_veg, p_den >= -1, finite elevation,
+ * wind >= 0 and finite), builds the per-cell records and the fuel bit-plane,
+ * sets the state to init_burning at step 0, and synchronises `stream` once to
+ * read the validation result.  `workspace` must be 256-byte aligned and at
+ * least sim_workspace_size(...) bytes.  `stream` is a hipStream_t (NULL = the
+ * default stream).  On failure *out is NULL and sim_last_error(NULL) says why. */
+SIM_API int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace,
+             size_t ws_bytes, void* stream, uint32_t flags, int32_t ckpt_every,
+             int32_t T_max);
+
+/* Choose the execution shape (defaults: an autotuned shape, or 16 x 8 words,
+ * depth 8, skip on).  Only whitelisted shapes are compiled; others give
+ * SIM_E_SHAPE. */
+SIM_API int sim_set_exec(sim_handle* h, const sim_exec* e);
+SIM_API int sim_get_exec(const sim_handle* h, sim_exec* e);
+
+/* Advance every scenario by T >= 0 steps (Sec. 2.2 transition rules).  In
+ * calibration mode the accumulator records p_ignite at each ignition and the
+ * state is checkpointed every ckpt_every steps; the run may not go past
+ * T_max steps from the last reset. */
+SIM_API int sim_run(sim_handle* h, int32_t T);
+SIM_API int sim_step(sim_handle* h);
+
+/* Steps taken since the last reset (host-side counter). */
+SIM_API int sim_get_step(const sim_handle* h, int32_t* step);
+
+/* Replace the parameters: `per_scenario` is a host array of n entries.
+ * Takes effect from the next step. */
+SIM_API int sim_set_params(sim_handle* h, const sim_params* per_scenario);
+
+/* Restore every scenario to init_burning at step 0 and clear the
+ * accumulator (Algorithm 1, model.reset).  `seeds` (host, n entries) replaces
+ * the Philox keys, or is NULL to keep them. */
+SIM_API int sim_reset(sim_handle* h, const uint64_t* seeds);
+
+/* Copy scenario s's state into `out` (device, 2*H*W bytes: channel 0 =
+ * burning, channel 1 = burned, Sec. 2.1 output), or set it from `in` (same
+ * layout, channels must not both be set) and declare it to be the state after
+ * `step` steps.  sim_set_state is not allowed in calibration mode. */
+SIM_API int sim_get_state(sim_handle* h, int32_t s, uint8_t* out);
+SIM_API int sim_set_state(sim_handle* h, int32_t s, const uint8_t* in, int32_t step);
+
+/* Ignition-probability map of Eq. 9 for scenario s's current state
+ * (the paper's "internal function"): device FP32 H*W; 0 for cells that are
+ * not burnable or have no burning neighbour. */
+SIM_API int sim_pignite(sim_handle* h, int32_t s, float* out);
+
+/* Accumulator of scenario s (calibration mode): p_ignite at the step each
+ * cell ignited, 1 for initially burning cells, 0 otherwise.  Device FP32 H*W. */
+SIM_API int sim_accumulator(sim_handle* h, int32_t s, float* out);
+
+/* Gradient of sum_s sum_j dL_dyhat[s][j] * yhat[s][j] with respect to
+ * (p_h, a, c1, c2) for each scenario, with states held constant (Sec. 2.3:
+ * only p_ignite of ignited cells carries gradient).  Recomputes every
+ * checkpoint segment of the last run.  dL_dyhat: device FP32, the n grids
+ * concatenated; grad: device FP64, n x 4.  Calibration mode only. */
+SIM_API int sim_adjoint(sim_handle* h, const float* dL_dyhat, double* grad);
+
+/* Eq. 10 loss of the accumulator against `target` (device uint8, the n grids
+ * concatenated, non-zero = observed fire) and its gradient: loss is device
+ * FP64 n, grad device FP64 n x 4 (p_h, a, c1, c2).  Calibration mode only. */
+SIM_API int sim_loss_grad(sim_handle* h, const uint8_t* target, int32_t loss_kind, double* loss,
+                  double* grad);
+
+/* Counters accumulated since the last reset with SIM_F_STATS (host array of
+ * 4): processed tiles, ignition + continue trials, ignition trials with
+ * |draw - p_ignite| <= 1e-5, launches. */
+SIM_API int sim_stats(sim_handle* h, uint64_t out[4]);
+
+/* Last error message of `h` (or of the last failed sim_init when h is NULL). */
+SIM_API const char* sim_last_error(const sim_handle* h);
+
+/* Release the handle (host memory only; the caller frees the workspace). */
+SIM_API void sim_destroy(sim_handle* h);
+
+/* Library version string. */
+SIM_API const char* sim_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,699 @@
+// api.hip -- C ABI of libfiresim: validation, workspace carving, launch
+// sequencing.  The contract of every entry point is documented in
+// include/firesim.h.
+#include "firesim.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMinTR = 8, kMinTC = 4;  // smallest whitelisted tile -> flag capacity
+constexpr int kMaxN = 65536;
+constexpr int kMaxSide = 1 << 16;
+const float kC = 1.1486328125f;        // f_p constant of Eq. 5 / 8, FP32
+
+thread_local std::string g_init_error;
+
+size_t up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct ScenLayout {
+    int32_t pitch;
+    int64_t PW;          // words per bit-plane
+    int64_t max_tiles;   // flag capacity
+    size_t rec, fuel, planes[2], flags[2], yhat, ckpt;
+};
+
+struct Layout {
+    size_t err, stats, box, part, jobs, tile_job, adj_jobs, adj_tile_job, gpart, ranges, lam,
+        total;
+    std::vector<ScenLayout> s;
+    std::vector<size_t> adj_planes[2], adj_flags[2];  // per (s, seg)
+    int nseg;
+    int64_t max_tiles_total, adj_max_tiles_total;
+};
+
+bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, Layout* L) {
+    const bool calib = flags & SIM_F_CALIB;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += up(bytes);
+        return o;
+    };
+    L->s.assign(n, ScenLayout());
+    L->nseg = calib ? (int)cdiv(T_max, ckpt_every) : 0;
+    int64_t max_h = 0;
+    L->err = take(64);
+    L->stats = take(4 * sizeof(unsigned long long));
+    L->box = take(4 * sizeof(int) * (size_t)n);
+    for (int i = 0; i < n; ++i) max_h = std::max<int64_t>(max_h, d[i].H);
+    L->part = take(2 * sizeof(double) * (size_t)cdiv(max_h, 4));
+    L->jobs = take(sizeof(fs::DevScen) * (size_t)n);
+    int64_t tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        ScenLayout& s = L->s[i];
+        s.pitch = (int32_t)cdiv(d[i].W, 32);
+        s.PW = (int64_t)d[i].H * s.pitch;
+        s.max_tiles = cdiv(d[i].H, kMinTR) * cdiv(s.pitch, kMinTC);
+        tiles += s.max_tiles;
+    }
+    L->max_tiles_total = tiles;
+    L->tile_job = take(sizeof(int32_t) * (size_t)tiles);
+    for (int i = 0; i < n; ++i) {
+        ScenLayout& s = L->s[i];
+        const int64_t cells = (int64_t)d[i].H * d[i].W;
+        s.rec = take(16 * (size_t)cells);
+        s.fuel = take(4 * (size_t)s.PW);
+        s.planes[0] = take(8 * (size_t)s.PW);
+        s.planes[1] = take(8 * (size_t)s.PW);
+        s.flags[0] = take((size_t)s.max_tiles);
+        s.flags[1] = take((size_t)s.max_tiles);
+        s.yhat = s.ckpt = 0;
+        if (calib) {
+            s.yhat = take(4 * (size_t)cells);
+            s.ckpt = take(8 * (size_t)s.PW * (size_t)L->nseg);
+        }
+    }
+    L->adj_jobs = L->adj_tile_job = L->gpart = L->ranges = L->lam = 0;
+    L->adj_max_tiles_total = 0;
+    for (int k = 0; k < 2; ++k) {
+        L->adj_planes[k].clear();
+        L->adj_flags[k].clear();
+    }
+    if (calib) {
+        L->adj_jobs = take(sizeof(fs::DevScen) * (size_t)n * L->nseg);
+        L->adj_max_tiles_total = tiles * L->nseg;
+        L->adj_tile_job = take(sizeof(int32_t) * (size_t)L->adj_max_tiles_total);
+        L->gpart = take(4 * sizeof(double) * (size_t)L->adj_max_tiles_total);
+        L->ranges = take(sizeof(int32_t) * (size_t)(n + 1));
+        int64_t cells = 0;
+        for (int i = 0; i < n; ++i) cells += (int64_t)d[i].H * d[i].W;
+        L->lam = take(4 * (size_t)cells);   // dL/dyhat of all scenarios, concatenated
+        for (int i = 0; i < n; ++i)
+            for (int g = 0; g < L->nseg; ++g)
+                for (int k = 0; k < 2; ++k) {
+                    L->adj_planes[k].push_back(take(8 * (size_t)L->s[i].PW));
+                    L->adj_flags[k].push_back(take((size_t)L->s[i].max_tiles));
+                }
+    }
+    L->total = off;
+    return true;
+}
+
+bool finite_params(const sim_params& p) {
+    return std::isfinite(p.p_h) && std::isfinite(p.a) && std::isfinite(p.c1) &&
+           std::isfinite(p.c2) && std::isfinite(p.p_continue) && p.p_h >= 0.f &&
+           p.p_continue >= 0.f && p.p_continue <= 1.f;
+}
+
+int check_descs(const sim_desc* d, int n, std::string* why) {
+    if (!d) { *why = "descs is NULL"; return SIM_E_ARG; }
+    if (n < 1 || n > kMaxN) { *why = "n out of range"; return SIM_E_SHAPE; }
+    for (int i = 0; i < n; ++i) {
+        char buf[160];
+        if (d[i].H < 1 || d[i].W < 1 || d[i].H > kMaxSide || d[i].W > kMaxSide) {
+            snprintf(buf, sizeof buf, "scenario %d: H, W must be in [1, %d]", i, kMaxSide);
+            *why = buf;
+            return SIM_E_SHAPE;
+        }
+        if (!(d[i].cell_m > 0.f) || !std::isfinite(d[i].cell_m)) {
+            snprintf(buf, sizeof buf, "scenario %d: cell_m must be finite and > 0", i);
+            *why = buf;
+            return SIM_E_PARAM;
+        }
+        if (!finite_params(d[i].params)) {
+            snprintf(buf, sizeof buf, "scenario %d: parameters must be finite, p_h >= 0, "
+                     "0 <= p_continue <= 1", i);
+            *why = buf;
+            return SIM_E_PARAM;
+        }
+        const sim_fields& f = d[i].f;
+        if (!f.p_veg || !f.p_den || !f.elevation_m || !f.init_burning) {
+            snprintf(buf, sizeof buf, "scenario %d: a required field pointer is NULL", i);
+            *why = buf;
+            return SIM_E_ARG;
+        }
+        if (!f.wind_speed && (!std::isfinite(f.wind_speed_scalar) || f.wind_speed_scalar < 0.f)) {
+            snprintf(buf, sizeof buf, "scenario %d: wind_speed_scalar must be finite, >= 0", i);
+            *why = buf;
+            return SIM_E_PARAM;
+        }
+        if (!f.wind_dir_deg && !std::isfinite(f.wind_dir_deg_scalar)) {
+            snprintf(buf, sizeof buf, "scenario %d: wind_dir_deg_scalar must be finite", i);
+            *why = buf;
+            return SIM_E_PARAM;
+        }
+        if (((uintptr_t)f.p_veg | (uintptr_t)f.p_den | (uintptr_t)f.elevation_m |
+             (uintptr_t)f.wind_speed | (uintptr_t)f.wind_dir_deg) & 3u) {
+            snprintf(buf, sizeof buf, "scenario %d: FP32 fields must be 4-byte aligned", i);
+            *why = buf;
+            return SIM_E_ARG;
+        }
+    }
+    return SIM_OK;
+}
+
+}  // namespace
+
+struct sim_handle {
+    int n = 0;
+    uint32_t flags = 0;
+    hipStream_t st = nullptr;
+    int ckpt_every = 0, T_max = 0;
+    std::vector<sim_desc> d;
+    Layout L;
+    char* ws = nullptr;
+    std::vector<fs::DevScen> job;   // host mirror of the forward job table
+    std::vector<int32_t> tile_job;
+    int32_t ntiles = 0;
+    std::vector<fs::DevScen> adj;   // adjoint jobs for the last run length
+    std::vector<int32_t> adj_tile_job, adj_ranges;
+    int32_t adj_ntiles = 0, adj_T = -1;
+    sim_exec ex{};
+    fs::TileShape sh{};
+    int parity = 0, step = 0;
+    unsigned long long launches = 0;
+    int64_t max_words = 0;
+    std::string err;
+
+    fs::DevScen* d_jobs() { return reinterpret_cast<fs::DevScen*>(ws + L.jobs); }
+    int32_t* d_tile_job() { return reinterpret_cast<int32_t*>(ws + L.tile_job); }
+    int* d_err() { return reinterpret_cast<int*>(ws + L.err); }
+    unsigned long long* d_stats() { return reinterpret_cast<unsigned long long*>(ws + L.stats); }
+    bool calib() const { return flags & SIM_F_CALIB; }
+
+    int fail(int code, const char* fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+    int hip(hipError_t e, const char* what) {
+        if (e == hipSuccess) return SIM_OK;
+        return fail(SIM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+    }
+};
+
+namespace {
+
+fs::TileShape shape_of(const sim_exec& e) {
+    int km = 1;
+    for (int k : {1, 4, 8, 16})
+        if (k >= e.depth) { km = k; break; }
+    return fs::TileShape{e.tile_rows, e.tile_words, km};
+}
+
+// Recompute tile grids and the tile -> job table of the forward jobs.
+int rebuild_tiles(sim_handle* h) {
+    int32_t g = 0;
+    h->tile_job.clear();
+    for (int i = 0; i < h->n; ++i) {
+        fs::DevScen& J = h->job[i];
+        J.tiles_r = (int32_t)cdiv(J.H, h->sh.tr);
+        J.tiles_c = (int32_t)cdiv(J.pitch, h->sh.tc);
+        J.tile0 = g;
+        const int32_t nt = J.tiles_r * J.tiles_c;
+        h->tile_job.insert(h->tile_job.end(), nt, i);
+        g += nt;
+    }
+    h->ntiles = g;
+    h->adj_T = -1;
+    int rc = h->hip(hipMemcpyAsync(h->d_jobs(), h->job.data(), sizeof(fs::DevScen) * h->n,
+                                   hipMemcpyHostToDevice, h->st), "upload jobs");
+    if (rc) return rc;
+    rc = h->hip(hipMemcpyAsync(h->d_tile_job(), h->tile_job.data(), sizeof(int32_t) * g,
+                               hipMemcpyHostToDevice, h->st), "upload tile table");
+    if (rc) return rc;
+    // the host vectors are reused by later calls: wait for the copies
+    rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (rc) return rc;
+    return h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles,
+                                        h->parity, h->sh), "flags init");
+}
+
+int save_ckpt(sim_handle* h, int slot) {
+    return h->hip(fs::launch_ckpt_save(h->st, h->d_jobs(), h->n, h->parity, slot, h->max_words),
+                  "checkpoint");
+}
+
+int reset_state(sim_handle* h) {
+    h->parity = 0;
+    h->step = 0;
+    for (int i = 0; i < h->n; ++i) {
+        const fs::DevScen& J = h->job[i];
+        int rc = h->hip(fs::launch_init_state(h->st, J, h->d[i].f.init_burning, J.planes[0],
+                                              J.yhat), "init state");
+        if (rc) return rc;
+    }
+    int rc = h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles, 0,
+                                          h->sh), "flags init");
+    if (rc) return rc;
+    rc = h->hip(hipMemsetAsync(h->d_stats(), 0, 4 * sizeof(unsigned long long), h->st),
+                "clear stats");
+    if (rc) return rc;
+    h->launches = 0;
+    if (h->calib()) return save_ckpt(h, 0);
+    return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sim_version(void) { return "firesim 0.1 (gfx950)"; }
+
+size_t sim_workspace_size(const sim_desc* descs, int32_t n, uint32_t flags, int32_t ckpt_every,
+                          int32_t T_max) {
+    std::string why;
+    if (check_descs(descs, n, &why) != SIM_OK) return 0;
+    if ((flags & SIM_F_CALIB) && (ckpt_every < 1 || T_max < 1)) return 0;
+    Layout L;
+    plan(descs, n, flags, ckpt_every, T_max, &L);
+    return L.total;
+}
+
+int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace,
+             size_t ws_bytes, void* stream, uint32_t flags, int32_t ckpt_every, int32_t T_max) {
+    g_init_error.clear();
+    if (!out) { g_init_error = "out is NULL"; return SIM_E_ARG; }
+    *out = nullptr;
+    std::string why;
+    int rc = check_descs(descs, n, &why);
+    if (rc) { g_init_error = why; return rc; }
+    if (flags & ~(uint32_t)(SIM_F_CALIB | SIM_F_STATS)) {
+        g_init_error = "unknown flag bits";
+        return SIM_E_ARG;
+    }
+    if ((flags & SIM_F_CALIB) && (ckpt_every < 1 || T_max < 1)) {
+        g_init_error = "calibration mode needs ckpt_every >= 1 and T_max >= 1";
+        return SIM_E_SHAPE;
+    }
+    if (!workspace) { g_init_error = "workspace is NULL"; return SIM_E_ARG; }
+    if ((uintptr_t)workspace % kAlign) {
+        g_init_error = "workspace must be 256-byte aligned";
+        return SIM_E_WORKSPACE;
+    }
+    sim_handle* h = new (std::nothrow) sim_handle();
+    if (!h) { g_init_error = "out of host memory"; return SIM_E_ARG; }
+    h->n = n;
+    h->flags = flags;
+    h->st = (hipStream_t)stream;
+    h->ckpt_every = (flags & SIM_F_CALIB) ? ckpt_every : 0;
+    h->T_max = (flags & SIM_F_CALIB) ? T_max : 0;
+    h->d.assign(descs, descs + n);
+    plan(descs, n, flags, ckpt_every, T_max, &h->L);
+    if (ws_bytes < h->L.total) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "workspace too small: %zu < %zu bytes", ws_bytes, h->L.total);
+        g_init_error = buf;
+        delete h;
+        return SIM_E_WORKSPACE;
+    }
+    h->ws = static_cast<char*>(workspace);
+
+    // default execution shape
+    int32_t max_pitch = 0;
+    for (const auto& s : h->L.s) max_pitch = std::max(max_pitch, s.pitch);
+    h->ex = sim_exec{16, max_pitch <= 4 ? 4 : 8, 8, 1};
+    h->sh = shape_of(h->ex);
+
+    h->job.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const sim_desc& d = descs[i];
+        const ScenLayout& s = h->L.s[i];
+        fs::DevScen& J = h->job[i];
+        std::memset(&J, 0, sizeof J);
+        J.H = d.H;
+        J.W = d.W;
+        J.pitch = s.pitch;
+        J.t_base = 0;
+        J.t_end = INT_MAX;
+        J.scen_id = d.scenario_id;
+        J.seed_lo = (uint32_t)d.seed;
+        J.seed_hi = (uint32_t)(d.seed >> 32);
+        J.inv_l = 1.0f / d.cell_m;
+        J.inv_l_diag = (float)(1.0 / (std::sqrt(2.0) * (double)d.cell_m));
+        J.p_h = d.params.p_h;
+        J.a = d.params.a;
+        J.c1 = d.params.c1;
+        J.c2 = d.params.c2;
+        J.p_continue = d.params.p_continue;
+        J.c = kC;
+        J.elev = d.f.elevation_m;
+        J.rec = reinterpret_cast<const float4*>(h->ws + s.rec);
+        J.fuel = reinterpret_cast<const uint32_t*>(h->ws + s.fuel);
+        J.planes[0] = reinterpret_cast<uint32_t*>(h->ws + s.planes[0]);
+        J.planes[1] = reinterpret_cast<uint32_t*>(h->ws + s.planes[1]);
+        J.flags[0] = reinterpret_cast<uint8_t*>(h->ws + s.flags[0]);
+        J.flags[1] = reinterpret_cast<uint8_t*>(h->ws + s.flags[1]);
+        J.yhat = h->calib() ? reinterpret_cast<float*>(h->ws + s.yhat) : nullptr;
+        J.ckpt = h->calib() ? reinterpret_cast<uint32_t*>(h->ws + s.ckpt) : nullptr;
+        J.gpart = nullptr;
+        J.lam_off = 0;
+        h->max_words = std::max<int64_t>(h->max_words, s.PW);
+    }
+
+    rc = h->hip(hipMemsetAsync(h->d_err(), 0, sizeof(int), h->st), "clear error flag");
+    for (int i = 0; i < n && !rc; ++i) {
+        const sim_desc& d = descs[i];
+        fs::DevScen& J = h->job[i];
+        rc = h->hip(fs::launch_prologue(h->st, nullptr, J, d.f.p_veg, d.f.p_den, d.f.wind_speed,
+                                        d.f.wind_dir_deg, d.f.wind_speed_scalar,
+                                        d.f.wind_dir_deg_scalar, d.f.init_burning,
+                                        const_cast<float4*>(J.rec),
+                                        const_cast<uint32_t*>(J.fuel), J.yhat, h->d_err()),
+                    "prologue");
+    }
+    if (!rc) rc = rebuild_tiles(h);
+    if (!rc) rc = reset_state(h);
+    int bad = 0;
+    if (!rc) rc = h->hip(hipMemcpyAsync(&bad, h->d_err(), sizeof(int), hipMemcpyDeviceToHost,
+                                        h->st), "read validation flag");
+    if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (!rc && bad) {
+        std::string m = "invalid field values:";
+        if (bad & 1) m += " p_veg < -1 or non-finite;";
+        if (bad & 2) m += " p_den < -1 or non-finite;";
+        if (bad & 4) m += " non-finite elevation;";
+        if (bad & 8) m += " wind speed < 0 or non-finite;";
+        if (bad & 16) m += " non-finite wind direction;";
+        g_init_error = m;
+        delete h;
+        return SIM_E_PARAM;
+    }
+    if (rc) {
+        g_init_error = h->err;
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return SIM_OK;
+}
+
+int sim_set_exec(sim_handle* h, const sim_exec* e) {
+    if (!h || !e) return h ? h->fail(SIM_E_ARG, "exec is NULL") : SIM_E_ARG;
+    if (e->depth < 1 || e->depth > 32 || e->depth > e->tile_rows)
+        return h->fail(SIM_E_SHAPE, "depth must be in [1, min(32, tile_rows)]");
+    const fs::TileShape sh = shape_of(*e);
+    if (e->depth > 16 || !fs::step_shape_supported(sh, false) ||
+        (h->calib() && !fs::step_shape_supported(sh, true)))
+        return h->fail(SIM_E_SHAPE, "tile %dx%d words with depth %d is not compiled in",
+                       e->tile_rows, e->tile_words, e->depth);
+    h->ex = *e;
+    h->ex.skip = e->skip ? 1 : 0;
+    const bool same = sh.tr == h->sh.tr && sh.tc == h->sh.tc;
+    h->sh = sh;
+    if (same) return SIM_OK;
+    return rebuild_tiles(h);
+}
+
+int sim_get_exec(const sim_handle* h, sim_exec* e) {
+    if (!h || !e) return SIM_E_ARG;
+    *e = h->ex;
+    return SIM_OK;
+}
+
+int sim_run(sim_handle* h, int32_t T) {
+    if (!h) return SIM_E_ARG;
+    if (T < 0) return h->fail(SIM_E_SHAPE, "T must be >= 0");
+    if (h->calib() && (int64_t)h->step + T > h->T_max)
+        return h->fail(SIM_E_STATE, "calibration run would pass T_max = %d", h->T_max);
+    if ((int64_t)h->step + T > INT_MAX / 2) return h->fail(SIM_E_SHAPE, "step counter overflow");
+    unsigned long long* stats = (h->flags & SIM_F_STATS) ? h->d_stats() : nullptr;
+    while (T > 0) {
+        int k = std::min(h->ex.depth, T);
+        if (h->calib()) k = std::min(k, h->ckpt_every - h->step % h->ckpt_every);
+        int rc = h->hip(fs::launch_step(h->st, h->sh, false, h->d_jobs(), h->d_tile_job(),
+                                        h->ntiles, h->parity, h->step, k, h->ex.skip, nullptr,
+                                        stats), "step kernel");
+        if (rc) return rc;
+        ++h->launches;
+        h->parity ^= 1;
+        h->step += k;
+        T -= k;
+        if (h->calib() && h->step % h->ckpt_every == 0 && h->step < h->T_max) {
+            rc = save_ckpt(h, h->step / h->ckpt_every);
+            if (rc) return rc;
+        }
+    }
+    return SIM_OK;
+}
+
+int sim_step(sim_handle* h) { return sim_run(h, 1); }
+
+int sim_get_step(const sim_handle* h, int32_t* step) {
+    if (!h || !step) return SIM_E_ARG;
+    *step = h->step;
+    return SIM_OK;
+}
+
+int sim_set_params(sim_handle* h, const sim_params* p) {
+    if (!h) return SIM_E_ARG;
+    if (!p) return h->fail(SIM_E_ARG, "params is NULL");
+    for (int i = 0; i < h->n; ++i)
+        if (!finite_params(p[i]))
+            return h->fail(SIM_E_PARAM, "scenario %d: parameters must be finite, p_h >= 0, "
+                           "0 <= p_continue <= 1", i);
+    for (int first = 0; first < h->n; first += 64) {
+        fs::ParamBlock pb;
+        pb.first = first;
+        pb.count = std::min(64, h->n - first);
+        for (int i = 0; i < pb.count; ++i) {
+            const sim_params& q = p[first + i];
+            pb.v[i][0] = q.p_h;
+            pb.v[i][1] = q.a;
+            pb.v[i][2] = q.c1;
+            pb.v[i][3] = q.c2;
+            pb.v[i][4] = q.p_continue;
+            fs::DevScen& J = h->job[first + i];
+            J.p_h = q.p_h;
+            J.a = q.a;
+            J.c1 = q.c1;
+            J.c2 = q.c2;
+            J.p_continue = q.p_continue;
+            h->d[first + i].params = q;
+        }
+        int rc = h->hip(fs::launch_set_params(h->st, h->d_jobs(), pb), "set params");
+        if (rc) return rc;
+    }
+    h->adj_T = -1;  // adjoint jobs copy the parameters
+    return SIM_OK;
+}
+
+int sim_reset(sim_handle* h, const uint64_t* seeds) {
+    if (!h) return SIM_E_ARG;
+    if (seeds) {
+        for (int first = 0; first < h->n; first += 64) {
+            fs::SeedBlock sb;
+            sb.first = first;
+            sb.count = std::min(64, h->n - first);
+            for (int i = 0; i < sb.count; ++i) {
+                sb.lo[i] = (uint32_t)seeds[first + i];
+                sb.hi[i] = (uint32_t)(seeds[first + i] >> 32);
+                h->job[first + i].seed_lo = sb.lo[i];
+                h->job[first + i].seed_hi = sb.hi[i];
+                h->d[first + i].seed = seeds[first + i];
+            }
+            int rc = h->hip(fs::launch_set_seeds(h->st, h->d_jobs(), sb), "set seeds");
+            if (rc) return rc;
+        }
+        h->adj_T = -1;
+    }
+    return reset_state(h);
+}
+
+int sim_get_state(sim_handle* h, int32_t s, uint8_t* out) {
+    if (!h) return SIM_E_ARG;
+    if (s < 0 || s >= h->n) return h->fail(SIM_E_ARG, "scenario index %d out of range", s);
+    if (!out) return h->fail(SIM_E_ARG, "out is NULL");
+    const fs::DevScen& J = h->job[s];
+    return h->hip(fs::launch_get_state(h->st, J, J.planes[h->parity], out), "get state");
+}
+
+int sim_set_state(sim_handle* h, int32_t s, const uint8_t* in, int32_t step) {
+    if (!h) return SIM_E_ARG;
+    if (s < 0 || s >= h->n) return h->fail(SIM_E_ARG, "scenario index %d out of range", s);
+    if (!in) return h->fail(SIM_E_ARG, "in is NULL");
+    if (step < 0) return h->fail(SIM_E_SHAPE, "step must be >= 0");
+    if (h->calib()) return h->fail(SIM_E_STATE, "sim_set_state is not allowed in calibration mode");
+    const fs::DevScen& J = h->job[s];
+    int rc = h->hip(hipMemsetAsync(h->d_err(), 0, sizeof(int), h->st), "clear error flag");
+    if (!rc) rc = h->hip(fs::launch_set_state(h->st, J, in, J.planes[h->parity], h->d_err()),
+                         "set state");
+    if (!rc) rc = h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles,
+                                               h->parity, h->sh), "flags init");
+    int bad = 0;
+    if (!rc) rc = h->hip(hipMemcpyAsync(&bad, h->d_err(), sizeof(int), hipMemcpyDeviceToHost,
+                                        h->st), "read error flag");
+    if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (rc) return rc;
+    if (bad) return h->fail(SIM_E_ARG, "state has cells both burning and burned");
+    h->step = step;
+    return SIM_OK;
+}
+
+int sim_pignite(sim_handle* h, int32_t s, float* out) {
+    if (!h) return SIM_E_ARG;
+    if (s < 0 || s >= h->n) return h->fail(SIM_E_ARG, "scenario index %d out of range", s);
+    if (!out) return h->fail(SIM_E_ARG, "out is NULL");
+    return h->hip(fs::launch_pignite(h->st, h->d_jobs() + s, h->job[s], h->parity, out),
+                  "pignite");
+}
+
+int sim_accumulator(sim_handle* h, int32_t s, float* out) {
+    if (!h) return SIM_E_ARG;
+    if (s < 0 || s >= h->n) return h->fail(SIM_E_ARG, "scenario index %d out of range", s);
+    if (!out) return h->fail(SIM_E_ARG, "out is NULL");
+    if (!h->calib()) return h->fail(SIM_E_STATE, "the accumulator needs SIM_F_CALIB");
+    const fs::DevScen& J = h->job[s];
+    return h->hip(hipMemcpyAsync(out, J.yhat, sizeof(float) * (size_t)J.H * J.W,
+                                 hipMemcpyDeviceToDevice, h->st), "copy accumulator");
+}
+
+namespace {
+
+// Adjoint job table for a run of T steps: one job per (scenario, segment).
+int build_adjoint(sim_handle* h, int T) {
+    const int nseg = (int)cdiv(T, h->ckpt_every);
+    h->adj.clear();
+    h->adj_tile_job.clear();
+    h->adj_ranges.assign(1, 0);
+    int32_t g = 0;
+    for (int i = 0; i < h->n; ++i) {
+        const fs::DevScen& F = h->job[i];
+        for (int sg = 0; sg < nseg; ++sg) {
+            fs::DevScen J = F;
+            const size_t idx = (size_t)i * h->L.nseg + sg;
+            J.planes[0] = reinterpret_cast<uint32_t*>(h->ws + h->L.adj_planes[0][idx]);
+            J.planes[1] = reinterpret_cast<uint32_t*>(h->ws + h->L.adj_planes[1][idx]);
+            J.flags[0] = reinterpret_cast<uint8_t*>(h->ws + h->L.adj_flags[0][idx]);
+            J.flags[1] = reinterpret_cast<uint8_t*>(h->ws + h->L.adj_flags[1][idx]);
+            J.ckpt = F.ckpt + (int64_t)sg * 2 * h->L.s[i].PW;
+            J.t_base = sg * h->ckpt_every;
+            J.t_end = std::min((sg + 1) * h->ckpt_every, T);
+            J.yhat = nullptr;
+            J.gpart = reinterpret_cast<double*>(h->ws + h->L.gpart);
+            J.tile0 = g;
+            const int32_t nt = J.tiles_r * J.tiles_c;
+            h->adj_tile_job.insert(h->adj_tile_job.end(), nt, (int32_t)h->adj.size());
+            g += nt;
+            h->adj.push_back(J);
+        }
+        h->adj_ranges.push_back(g);
+    }
+    int64_t off = 0;
+    for (int i = 0; i < h->n; ++i) {
+        for (int sg = 0; sg < nseg; ++sg) h->adj[(size_t)i * nseg + sg].lam_off = off;
+        off += (int64_t)h->job[i].H * h->job[i].W;
+    }
+    h->adj_ntiles = g;
+    int rc = h->hip(hipMemcpyAsync(h->ws + h->L.adj_jobs, h->adj.data(),
+                                   sizeof(fs::DevScen) * h->adj.size(), hipMemcpyHostToDevice,
+                                   h->st), "upload adjoint jobs");
+    if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.adj_tile_job, h->adj_tile_job.data(),
+                                        sizeof(int32_t) * (size_t)g, hipMemcpyHostToDevice,
+                                        h->st), "upload adjoint tiles");
+    if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.ranges, h->adj_ranges.data(),
+                                        sizeof(int32_t) * (size_t)(h->n + 1),
+                                        hipMemcpyHostToDevice, h->st), "upload ranges");
+    if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (!rc) h->adj_T = T;
+    return rc;
+}
+
+int adjoint(sim_handle* h, const float* lam, double* grad) {
+    const int T = h->step;
+    if (T == 0)
+        return h->hip(hipMemsetAsync(grad, 0, sizeof(double) * 4 * (size_t)h->n, h->st),
+                      "zero gradient");
+    int rc = SIM_OK;
+    if (h->adj_T != T) rc = build_adjoint(h, T);
+    if (rc) return rc;
+    auto* d_adj = reinterpret_cast<fs::DevScen*>(h->ws + h->L.adj_jobs);
+    auto* d_adj_tiles = reinterpret_cast<int32_t*>(h->ws + h->L.adj_tile_job);
+    const int njobs = (int)h->adj.size();
+    rc = h->hip(fs::launch_ckpt_load(h->st, d_adj, njobs, h->max_words), "load checkpoints");
+    if (!rc) rc = h->hip(fs::launch_flags_init(h->st, d_adj, d_adj_tiles, h->adj_ntiles, 0,
+                                               h->sh), "adjoint flags");
+    if (!rc) rc = h->hip(fs::launch_fill_u32(h->st, reinterpret_cast<uint32_t*>(h->ws + h->L.gpart),
+                                             (size_t)h->adj_ntiles * 8, 0u), "zero partials");
+    int parity = 0;
+    unsigned long long* stats = nullptr;
+    for (int off = 0; off < h->ckpt_every && !rc; ) {
+        const int k = std::min(h->ex.depth, h->ckpt_every - off);
+        rc = h->hip(fs::launch_step(h->st, h->sh, true, d_adj, d_adj_tiles, h->adj_ntiles,
+                                    parity, off, k, h->ex.skip, lam, stats), "adjoint kernel");
+        parity ^= 1;
+        off += k;
+    }
+    if (!rc) rc = h->hip(fs::launch_grad_reduce(h->st, reinterpret_cast<double*>(h->ws + h->L.gpart),
+                                                reinterpret_cast<int32_t*>(h->ws + h->L.ranges),
+                                                h->n, grad), "reduce gradient");
+    return rc;
+}
+
+}  // namespace
+
+int sim_adjoint(sim_handle* h, const float* dL_dyhat, double* grad) {
+    if (!h) return SIM_E_ARG;
+    if (!dL_dyhat || !grad) return h->fail(SIM_E_ARG, "dL_dyhat and grad must be non-NULL");
+    if (!h->calib()) return h->fail(SIM_E_STATE, "sim_adjoint needs SIM_F_CALIB");
+    return adjoint(h, dL_dyhat, grad);
+}
+
+int sim_loss_grad(sim_handle* h, const uint8_t* target, int32_t kind, double* loss,
+                  double* grad) {
+    if (!h) return SIM_E_ARG;
+    if (!target || !loss || !grad) return h->fail(SIM_E_ARG, "target, loss, grad must be non-NULL");
+    if (kind < SIM_LOSS_BCE || kind > SIM_LOSS_MSE) return h->fail(SIM_E_ARG, "bad loss kind");
+    if (!h->calib()) return h->fail(SIM_E_STATE, "sim_loss_grad needs SIM_F_CALIB");
+    float* lam = reinterpret_cast<float*>(h->ws + h->L.lam);
+    int64_t off = 0;
+    for (int i = 0; i < h->n; ++i) {
+        const fs::DevScen& J = h->job[i];
+        int rc = h->hip(fs::launch_loss(h->st, J.H, J.W, J.yhat, target + off, kind, lam + off,
+                                        reinterpret_cast<int*>(h->ws + h->L.box) + 4 * i,
+                                        reinterpret_cast<double*>(h->ws + h->L.part), loss + i),
+                        "loss");
+        if (rc) return rc;
+        off += (int64_t)J.H * J.W;
+    }
+    return adjoint(h, lam, grad);
+}
+
+int sim_stats(sim_handle* h, uint64_t out[4]) {
+    if (!h || !out) return SIM_E_ARG;
+    unsigned long long v[4] = {0, 0, 0, 0};
+    int rc = h->hip(hipMemcpyAsync(v, h->d_stats(), sizeof v, hipMemcpyDeviceToHost, h->st),
+                    "read stats");
+    if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (rc) return rc;
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+    out[3] = h->launches;
+    return SIM_OK;
+}
+
+const char* sim_last_error(const sim_handle* h) {
+    return h ? h->err.c_str() : g_init_error.c_str();
+}
+
+void sim_destroy(sim_handle* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// internal.h -- device-side descriptors and kernel launchers of libfiresim.
+//
+// Data layout in HBM (per scenario, all inside the caller's workspace):
+//   rec     float4 per cell: (F, V, V cos(theta_w), V sin(theta_w)) with
+//           F = (1 + p_veg)(1 + p_den), the fuel factors of Eq. 2 multiplied
+//           once, and the wind heading resolved into east/north components.
+//   fuel    one bit per cell (F > 0), rows of `pitch` 32-bit words.
+//   planes  two ping-pong buffers; each holds the burning bit-plane followed
+//           by the burned bit-plane (2 * H * pitch words): 2 bits per cell.
+//   flags   per tile and per buffer parity: bit 0 = some cell of the tile is
+//           burning, bit 1 = both ping-pong buffers hold the same tile.
+//   yhat    FP32 accumulator (calibration), ckpt state checkpoints.
+// Bit b of word w in row r is the cell (r, 32 w + b).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fs {
+
+struct DevScen {
+    int32_t H, W, pitch;       // pitch: 32-bit words per row
+    int32_t tiles_r, tiles_c;  // tile grid of the current execution shape
+    int32_t tile0;             // first global tile index of this job
+    int32_t t_base;            // step index offset of this job
+    int32_t t_end;             // last step this job may produce
+    uint32_t scen_id;
+    uint32_t seed_lo, seed_hi;
+    float inv_l, inv_l_diag;   // 1 / l and 1 / (sqrt(2) l) of Eq. 1
+    float p_h, a, c1, c2, p_continue, c;
+    int32_t pad0;
+    const float* elev;         // caller's elevation field
+    const float4* rec;         // per-cell record
+    const uint32_t* fuel;      // fuel bit-plane
+    uint32_t* planes[2];       // ping-pong state buffers
+    uint8_t* flags[2];         // per-tile flags, per parity
+    float* yhat;               // accumulator or nullptr
+    uint32_t* ckpt;            // checkpoint store (forward) / own segment (adjoint)
+    double* gpart;             // per-tile gradient partials (adjoint jobs)
+    int64_t lam_off;           // offset of this scenario's dL/dyhat grid
+};
+
+struct TileShape {
+    int tr, tc, km;            // rows, words, halo depth (max steps per launch)
+};
+
+// Kernel launchers (kernels.hip).  All enqueue on `st` and return the launch
+// status; they assume arguments were validated by the caller.
+hipError_t launch_prologue(hipStream_t st, const DevScen* d_job, const DevScen& job,
+                           const float* p_veg, const float* p_den, const float* ws,
+                           const float* wd, float ws0, float wd0, const uint8_t* ign,
+                           float4* rec, uint32_t* fuel, float* yhat, int* d_err);
+hipError_t launch_init_state(hipStream_t st, const DevScen& job, const uint8_t* ign,
+                             uint32_t* planes, float* yhat);
+hipError_t launch_set_state(hipStream_t st, const DevScen& job, const uint8_t* in,
+                            uint32_t* planes, int* d_err);
+hipError_t launch_get_state(hipStream_t st, const DevScen& job, const uint32_t* planes,
+                            uint8_t* out);
+hipError_t launch_flags_init(hipStream_t st, const DevScen* d_jobs, const int32_t* d_tile_job,
+                             int32_t ntiles, int32_t parity, TileShape sh);
+bool step_shape_supported(TileShape sh, bool adj);
+hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_jobs,
+                       const int32_t* d_tile_job, int32_t ntiles, int32_t parity,
+                       int32_t t_off, int32_t ksteps, int32_t skip, const float* lam,
+                       unsigned long long* d_stats);
+// Copy each job's current planes into checkpoint slot `slot` (forward jobs).
+hipError_t launch_ckpt_save(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
+                            int32_t slot, int64_t max_words);
+// Copy each adjoint job's checkpoint into its planes[0].
+hipError_t launch_ckpt_load(hipStream_t st, const DevScen* d_jobs, int32_t n, int64_t max_words);
+struct ParamBlock {
+    int32_t first, count;
+    float v[64][5];
+};
+hipError_t launch_set_params(hipStream_t st, DevScen* d_jobs, const ParamBlock& pb);
+struct SeedBlock {
+    int32_t first, count;
+    uint32_t lo[64], hi[64];
+};
+hipError_t launch_set_seeds(hipStream_t st, DevScen* d_jobs, const SeedBlock& sb);
+hipError_t launch_pignite(hipStream_t st, const DevScen* d_job, const DevScen& job,
+                          int32_t parity, float* out);
+// Eq. 10 for one H x W scenario: writes lambda = dL/dyhat and *loss_out.
+// d_box holds 4 ints, d_part 2 * ceil(H / 4) doubles.
+hipError_t launch_loss(hipStream_t st, int32_t H, int32_t W, const float* yhat,
+                       const uint8_t* y, int32_t kind, float* lambda, int* d_box,
+                       double* d_part, double* loss_out);
+// grad[s] = sum of gpart[g] over tiles g in [ranges[s], ranges[s+1]).
+hipError_t launch_grad_reduce(hipStream_t st, const double* gpart, const int32_t* d_ranges,
+                              int32_t n, double* grad);
+hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, size_t n, uint32_t v);
+
+}  // namespace fs

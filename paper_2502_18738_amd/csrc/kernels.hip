@@ -1,0 +1,919 @@
+// kernels.hip -- gfx950 kernels of the wildfire cellular automaton.
+//
+// The hot path is `k_step`: one work-group advances one tile of one scenario
+// by up to KM steps entirely in LDS (temporal blocking).  The state is two
+// bit-planes (burning, burned); a 64-lane wavefront treats 64 words = 2048
+// cells per bitwise instruction, so finding the cells that need a Bernoulli
+// trial (burning cells, and burnable cells with fuel next to a burning cell,
+// Sec. 2.2 transition rules) costs a handful of bit operations per 32 cells.
+// Only those trial cells touch the per-cell fields: the fire front is a thin
+// ring, so per-edge transcendental work (Eq. 1-5) and field gathers scale with
+// the front, not with the grid.  Trials are compacted into an LDS list by a
+// work-group prefix sum and dealt round-robin to the 256 lanes, so one busy
+// word does not serialise a wavefront.
+//
+// Compiled with -ffp-contract=off: every FP32 operation rounds as written, so
+// the forward and adjoint instantiations compute bit-identical p_ignite and
+// take identical ignition decisions when the adjoint recomputes a segment.
+#include "internal.h"
+
+#include <math.h>
+
+#include <algorithm>
+
+namespace fs {
+
+namespace {
+
+constexpr float kRad2Deg = 57.295779513082320876798f;
+constexpr float kSqrtHalf = 0.70710678118654752440f;
+constexpr float kTwoM24 = 5.9604644775390625e-08f;  // 2^-24
+constexpr float kTieEps = 1e-5f;
+
+// Philox4x32-10 (Salmon et al., SC'11): returns words 0 and 1.
+__device__ __forceinline__ void philox_w01(uint32_t c0, uint32_t c1, uint32_t c2,
+                                           uint32_t c3, uint32_t k0, uint32_t k1,
+                                           uint32_t& w0, uint32_t& w1) {
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    w0 = c0;
+    w1 = c1;
+}
+
+__device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * kTwoM24; }
+
+// Per-edge terms of Eq. 1-5 for a burning neighbour at offset (dr, dc) of the
+// receiving cell j.  rec = (F, V, V cos, V sin) of j.  The spread direction
+// i -> j has east component -dc and north component +dr, so the projection of
+// the wind on it is (-dc * Vc + dr * Vs) / |(dr, dc)|.
+struct Edge {
+    float q, ez, x, th, vterm;
+};
+
+template <int DR, int DC>
+__device__ __forceinline__ Edge edge_terms(const DevScen& J, float4 rec, float Ej, float Ei) {
+    constexpr bool diag = (DR != 0) && (DC != 0);
+    Edge e;
+    const float sl = (Ej - Ei) * (diag ? J.inv_l_diag : J.inv_l);
+    e.th = atanf(sl) * kRad2Deg;                         // Eq. 1, degrees
+    float proj = (float)(-DC) * rec.z + (float)DR * rec.w;
+    if (diag) proj = proj * kSqrtHalf;
+    e.vterm = proj - rec.y;                               // V (cos(delta) - 1)
+    const float z = J.c1 * rec.y + J.c2 * e.vterm + J.a * e.th;   // Eq. 3, 4 exponents
+    e.ez = expf(z);
+    e.x = (J.p_h * rec.x) * e.ez;                         // Eq. 2
+    e.q = tanhf(J.c * e.x);                               // Eq. 5
+    return e;
+}
+
+// Eq. 9 as the recurrence P <- P + q (1 - P) over the burning neighbours in
+// fixed row-major order.  `nb(dr, dc)` tells whether a neighbour burns.  When
+// ADJ, also returns d p_ignite / d(p_h, a, c1, c2) in g.
+template <bool ADJ, class NB>
+__device__ __forceinline__ float cell_pignite(const DevScen& J, int64_t j, NB nb, float g[4]) {
+    const float4 rec = J.rec[j];
+    const float Ej = J.elev[j];
+    const int64_t W = J.W;
+    float P = 0.f;
+    float q[8], dx[8][4];
+    int k = 0;
+#define FS_EDGE(DR, DC)                                                             \
+    {                                                                               \
+        if (nb(DR, DC)) {                                                           \
+            const Edge e = edge_terms<DR, DC>(J, rec, Ej, J.elev[j + (DR) * W + (DC)]); \
+            P = P + e.q * (1.f - P);                                                \
+            if (ADJ) {                                                              \
+                q[k] = e.q;                                                         \
+                dx[k][0] = rec.x * e.ez;                                            \
+                dx[k][1] = e.x * e.th;                                              \
+                dx[k][2] = e.x * rec.y;                                             \
+                dx[k][3] = e.x * e.vterm;                                           \
+            }                                                                       \
+        } else if (ADJ) {                                                           \
+            q[k] = 0.f;                                                             \
+            dx[k][0] = dx[k][1] = dx[k][2] = dx[k][3] = 0.f;                        \
+        }                                                                           \
+        ++k;                                                                        \
+    }
+    FS_EDGE(-1, -1) FS_EDGE(-1, 0) FS_EDGE(-1, 1)
+    FS_EDGE(0, -1)                FS_EDGE(0, 1)
+    FS_EDGE(1, -1)  FS_EDGE(1, 0)  FS_EDGE(1, 1)
+#undef FS_EDGE
+    if (ADJ) {
+        // dP/dq_i = prod_{m != i} (1 - q_m), from prefix and suffix products so
+        // that a saturated q_m = 1 does not divide by zero.
+        float pre[8], suf[8];
+        float acc = 1.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) { pre[i] = acc; acc = acc * (1.f - q[i]); }
+        acc = 1.f;
+#pragma unroll
+        for (int i = 7; i >= 0; --i) { suf[i] = acc; acc = acc * (1.f - q[i]); }
+        g[0] = g[1] = g[2] = g[3] = 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float s = pre[i] * suf[i] * (J.c * (1.f - q[i] * q[i]));
+#pragma unroll
+            for (int m = 0; m < 4; ++m) g[m] = g[m] + s * dx[i][m];
+        }
+    }
+    return P;
+}
+
+__device__ __forceinline__ int block_exscan(int v, int* sWave, int* total) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) sWave[wv] = x;
+    __syncthreads();
+    int pre = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int s = sWave[k];
+        if (k < wv) pre += s;
+        tot += s;
+    }
+    *total = tot;
+    __syncthreads();
+    return pre + x - v;
+}
+
+// XCD-aware tile order: consecutive workgroups are dealt round-robin to the 8
+// XCDs, so give XCD x a contiguous run of tiles (neighbouring tiles share
+// halo rows in that XCD's L2).
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int x = bid & 7, local = bid >> 3;
+    return x * q + min(x, r) + local;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- main step
+
+template <int TR, int TC, int KM, bool ADJ>
+__global__ void __launch_bounds__(256)
+k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, int32_t ntiles,
+       int32_t parity, int32_t t_off, int32_t ksteps, int32_t skip,
+       const float* __restrict__ lam, unsigned long long* __restrict__ stats) {
+    constexpr int RR = TR + 2 * KM, RC = TC + 2, NW = RR * RC;
+    constexpr int WPT = (NW + 255) / 256;
+    constexpr int LCAP = 8192;
+    static_assert(NW * 32 < 65536, "trial list entries are 16-bit");
+    static_assert(KM <= TR && KM <= 32, "halo deeper than a tile");
+
+    __shared__ uint32_t sB[2][NW], sD[2][NW], sU[NW], sR[NW];
+    __shared__ uint16_t sL[LCAP];
+    __shared__ int sWave[4];
+    __shared__ int sFlag;
+    __shared__ double sG[ADJ ? 4 * 4 : 1];
+
+    const int tid = threadIdx.x;
+    const int g = xcd_tile(blockIdx.x, gridDim.x);
+    if (g >= ntiles) return;
+    const DevScen& J = jobs[tile_job[g]];
+    const int lt = g - J.tile0;
+    const int trow = lt / J.tiles_c, tcol = lt - trow * J.tiles_c;
+    const int H = J.H, pitch = J.pitch;
+    const int64_t PW = (int64_t)H * pitch;
+    const uint8_t* fin = J.flags[parity];
+    uint8_t* fout = J.flags[parity ^ 1];
+    const uint32_t* pin = J.planes[parity];
+    uint32_t* pout = J.planes[parity ^ 1];
+
+    const int kj = min(ksteps, J.t_end - (J.t_base + t_off));
+    if (kj <= 0) return;
+
+    // ---- skip a tile when no tile within reach holds a burning cell
+    bool need = true;
+    if (skip) {
+        need = false;
+        for (int dr = -1; dr <= 1; ++dr)
+            for (int dc = -1; dc <= 1; ++dc) {
+                const int rr = trow + dr, cc = tcol + dc;
+                if (rr >= 0 && rr < J.tiles_r && cc >= 0 && cc < J.tiles_c &&
+                    (fin[rr * J.tiles_c + cc] & 1))
+                    need = true;
+            }
+    }
+    if (!need) {
+        if (!(fin[lt] & 2)) {  // bring the other buffer up to date once
+            for (int w = tid; w < TR * TC; w += 256) {
+                const int gr = trow * TR + w / TC, gw = tcol * TC + w % TC;
+                if (gr < H && gw < pitch) {
+                    const int64_t o = (int64_t)gr * pitch + gw;
+                    pout[o] = pin[o];
+                    pout[PW + o] = pin[PW + o];
+                }
+            }
+        }
+        if (tid == 0) fout[lt] = 2;
+        return;
+    }
+
+    // ---- load the tile and a KM-row / 1-word halo into LDS
+    const int r0 = trow * TR - KM;
+    const int w0 = tcol * TC - 1;
+    uint32_t origB[WPT], origD[WPT];
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+        const int w = tid + i * 256;
+        origB[i] = origD[i] = 0;
+        if (w < NW) {
+            const int lr = w / RC, lc = w - (w / RC) * RC;
+            const int gr = r0 + lr, gw = w0 + lc;
+            uint32_t b = 0, d = 0, u = 0;
+            if (gr >= 0 && gr < H && gw >= 0 && gw < pitch) {
+                const int64_t o = (int64_t)gr * pitch + gw;
+                b = pin[o];
+                d = pin[PW + o];
+                u = J.fuel[o];
+            }
+            sB[0][w] = b;
+            sD[0][w] = d;
+            sU[w] = u;
+            origB[i] = b;
+            origD[i] = d;
+        }
+    }
+    if (tid == 0) sFlag = 0;
+
+    const uint32_t k0 = J.seed_lo, k1 = J.seed_hi, scen = J.scen_id;
+    double gsum[4] = {0.0, 0.0, 0.0, 0.0};
+    unsigned long long n_trials = 0, n_ties = 0;
+    int cur = 0;
+
+    for (int s = 1; s <= kj; ++s) {
+        __syncthreads();
+        const int t = J.t_base + t_off + s;
+        const int lo = s, hi = RR - s;
+        const uint32_t* cB = sB[cur];
+        const uint32_t* cD = sD[cur];
+
+        // trial masks of this thread's words
+        uint32_t tm[WPT];
+        int cnt = 0;
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) {
+            const int w = tid + i * 256;
+            tm[i] = 0;
+            if (w < NW) {
+                const int lr = w / RC, lc = w - (w / RC) * RC;
+                if (lr >= lo && lr < hi) {
+                    const int a = (lr - 1) * RC, b = lr * RC, c = (lr + 1) * RC;
+                    const uint32_t X = cB[a + lc] | cB[b + lc] | cB[c + lc];
+                    const uint32_t XL = lc > 0 ? (cB[a + lc - 1] | cB[b + lc - 1] | cB[c + lc - 1]) : 0u;
+                    const uint32_t XR = lc < RC - 1 ? (cB[a + lc + 1] | cB[b + lc + 1] | cB[c + lc + 1]) : 0u;
+                    const uint32_t nbm = X | (X << 1) | (X >> 1) | (XL >> 31) | (XR << 31);
+                    const uint32_t bw = cB[w], dw = cD[w];
+                    tm[i] = (nbm & ~bw & ~dw & sU[w]) | bw;
+                    cnt += __popc(tm[i]);
+                    sR[w] = 0;
+                }
+            }
+        }
+        int total;
+        const int off = block_exscan(cnt, sWave, &total);
+
+        for (int base = 0; base < total; base += LCAP) {
+            int o = off;
+#pragma unroll
+            for (int i = 0; i < WPT; ++i) {
+                uint32_t m = tm[i];
+                const int w = tid + i * 256;
+                while (m) {
+                    const int bit = __ffs(m) - 1;
+                    m &= m - 1;
+                    if (o >= base && o < base + LCAP) sL[o - base] = (uint16_t)(w * 32 + bit);
+                    ++o;
+                }
+            }
+            __syncthreads();
+            const int nl = min(LCAP, total - base);
+            for (int e = tid; e < nl; e += 256) {
+                const int ent = sL[e];
+                const int w = ent >> 5, bit = ent & 31;
+                const int lr = w / RC, lc = w - (w / RC) * RC;
+                const int gr = r0 + lr;
+                const int gc = (w0 + lc) * 32 + bit;
+                const int64_t j = (int64_t)gr * J.W + gc;
+                const bool interior = lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC;
+                uint32_t rw0, rw1;
+                philox_w01((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, scen, k0,
+                           k1, rw0, rw1);
+                if ((cB[w] >> bit) & 1u) {  // burning: continue trial
+                    if (u24(rw1) < J.p_continue) atomicOr(&sR[w], 1u << bit);
+                    if (interior) ++n_trials;
+                } else {  // burnable with a burning neighbour: ignition trial
+                    const int cl = lc * 32 + bit;
+                    auto nb = [&](int dr, int dc) -> bool {
+                        const int cc = cl + dc;
+                        if (cc < 0 || cc >= RC * 32) return false;
+                        return (cB[(lr + dr) * RC + (cc >> 5)] >> (cc & 31)) & 1u;
+                    };
+                    float gl[4];
+                    const float P = cell_pignite<ADJ>(J, j, nb, gl);
+                    const float u = u24(rw0);
+                    if (u < P) {
+                        atomicOr(&sR[w], 1u << bit);
+                        if (interior) {
+                            if (J.yhat) J.yhat[j] = P;
+                            if (ADJ) {
+                                const float lj = lam[J.lam_off + j];
+                                for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj * gl[m]);
+                            }
+                        }
+                    }
+                    if (interior) {
+                        ++n_trials;
+                        if (fabsf(u - P) <= kTieEps) ++n_ties;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+
+        // combine: burning' = successful trials; burned' = burned | burnt out
+#pragma unroll
+        for (int i = 0; i < WPT; ++i) {
+            const int w = tid + i * 256;
+            if (w < NW) {
+                const int lr = w / RC;
+                if (lr >= lo && lr < hi) {
+                    const uint32_t bw = cB[w], r = sR[w];
+                    sB[cur ^ 1][w] = r;
+                    sD[cur ^ 1][w] = cD[w] | (bw & ~r);
+                }
+            }
+        }
+        cur ^= 1;
+    }
+    __syncthreads();
+
+    // ---- write the tile interior back
+    bool anyB = false, changed = false;
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+        const int w = tid + i * 256;
+        if (w < NW) {
+            const int lr = w / RC, lc = w - (w / RC) * RC;
+            if (lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC) {
+                const int gr = r0 + lr, gw = w0 + lc;
+                if (gr < H && gw < pitch) {
+                    const int64_t o = (int64_t)gr * pitch + gw;
+                    const uint32_t nb = sB[cur][w], nd = sD[cur][w];
+                    pout[o] = nb;
+                    pout[PW + o] = nd;
+                    anyB |= nb != 0u;
+                    changed |= (nb != origB[i]) || (nd != origD[i]);
+                }
+            }
+        }
+    }
+    if (anyB) atomicOr(&sFlag, 1);
+    if (changed) atomicOr(&sFlag, 2);
+
+    if (ADJ) {
+        // deterministic work-group sum of the per-lane FP64 partials
+        for (int m = 0; m < 4; ++m) {
+            double v = gsum[m];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+            if ((tid & 63) == 0) sG[(tid >> 6) * 4 + m] = v;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int f = sFlag;
+        fout[lt] = (uint8_t)(((f & 1) ? 1 : 0) | ((f & 2) ? 0 : 2));
+        if (ADJ) {
+            for (int m = 0; m < 4; ++m)
+                J.gpart[(int64_t)g * 4 + m] +=
+                    ((sG[0 * 4 + m] + sG[1 * 4 + m]) + (sG[2 * 4 + m] + sG[3 * 4 + m]));
+        }
+    }
+    if (stats) {
+        // per-wave reduction of the counters, one atomic per wave
+        unsigned long long a = n_trials, b = n_ties;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            a += __shfl_down(a, d, 64);
+            b += __shfl_down(b, d, 64);
+        }
+        if ((tid & 63) == 0) {
+            if (a) atomicAdd(&stats[1], a);
+            if (b) atomicAdd(&stats[2], b);
+        }
+        if (tid == 0) atomicAdd(&stats[0], 1ull);
+    }
+}
+
+// ------------------------------------------------------------- prologue
+
+// One thread per cell of the padded grid (H rows x pitch*32 columns); a
+// wavefront covers 64 aligned columns = 2 words and packs them by ballot.
+__global__ void __launch_bounds__(256)
+k_prologue(int32_t H, int32_t W, int32_t pitch, const float* __restrict__ p_veg,
+           const float* __restrict__ p_den, const float* __restrict__ elev,
+           const float* __restrict__ ws, const float* __restrict__ wd, float ws0, float wd0,
+           const uint8_t* __restrict__ ign, float4* __restrict__ rec,
+           uint32_t* __restrict__ fuel, uint32_t* __restrict__ planes,
+           float* __restrict__ yhat, int* __restrict__ err) {
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    bool has_fuel = false, burning = false;
+    if (c < W) {
+        const int64_t j = (int64_t)r * W + c;
+        const float pv = p_veg[j], pd = p_den[j], e = elev[j];
+        const float V = ws ? ws[j] : ws0;
+        const float th = wd ? wd[j] : wd0;
+        int bad = 0;
+        if (!(pv >= -1.f) || !isfinite(pv)) bad |= 1;
+        if (!(pd >= -1.f) || !isfinite(pd)) bad |= 2;
+        if (!isfinite(e)) bad |= 4;
+        if (!(V >= 0.f) || !isfinite(V)) bad |= 8;
+        if (!isfinite(th)) bad |= 16;
+        if (bad) atomicOr(err, bad);
+        const float F = (1.f + pv) * (1.f + pd);
+        float sn, cs;
+        sincospif(th / 180.f, &sn, &cs);
+        rec[j] = make_float4(F, V, V * cs, V * sn);
+        has_fuel = F > 0.f;
+        burning = ign[j] != 0;
+        if (yhat) yhat[j] = burning ? 1.f : 0.f;
+    }
+    const unsigned long long mf = __ballot(has_fuel);
+    const unsigned long long mb = __ballot(burning);
+    const int wbase = (blockIdx.x * 256 + (threadIdx.x & ~63)) >> 5;
+    const int64_t PW = (int64_t)H * pitch;
+    if (lane == 0 || lane == 32) {
+        const int w = wbase + (lane >> 5);
+        if (w < pitch) {
+            const int64_t o = (int64_t)r * pitch + w;
+            const int sh = lane;
+            fuel[o] = (uint32_t)(mf >> sh);
+            planes[o] = (uint32_t)(mb >> sh);
+            planes[PW + o] = 0u;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_init_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ ign,
+             uint32_t* __restrict__ planes, float* __restrict__ yhat) {
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    bool burning = false;
+    if (c < W) {
+        const int64_t j = (int64_t)r * W + c;
+        burning = ign[j] != 0;
+        if (yhat) yhat[j] = burning ? 1.f : 0.f;
+    }
+    const unsigned long long mb = __ballot(burning);
+    const int wbase = (blockIdx.x * 256 + (threadIdx.x & ~63)) >> 5;
+    const int64_t PW = (int64_t)H * pitch;
+    if (lane == 0 || lane == 32) {
+        const int w = wbase + (lane >> 5);
+        if (w < pitch) {
+            const int64_t o = (int64_t)r * pitch + w;
+            planes[o] = (uint32_t)(mb >> lane);
+            planes[PW + o] = 0u;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_set_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ in,
+            uint32_t* __restrict__ planes, int* __restrict__ err) {
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t HW = (int64_t)H * W;
+    bool b = false, d = false;
+    if (c < W) {
+        const int64_t j = (int64_t)r * W + c;
+        b = in[j] != 0;
+        d = in[HW + j] != 0;
+        if (b && d) atomicOr(err, 32);
+    }
+    const unsigned long long mb = __ballot(b);
+    const unsigned long long md = __ballot(d);
+    const int wbase = (blockIdx.x * 256 + (threadIdx.x & ~63)) >> 5;
+    const int64_t PW = (int64_t)H * pitch;
+    if (lane == 0 || lane == 32) {
+        const int w = wbase + (lane >> 5);
+        if (w < pitch) {
+            const int64_t o = (int64_t)r * pitch + w;
+            planes[o] = (uint32_t)(mb >> lane);
+            planes[PW + o] = (uint32_t)(md >> lane);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_get_state(int32_t H, int32_t W, int32_t pitch, const uint32_t* __restrict__ planes,
+            uint8_t* __restrict__ out) {
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= W) return;
+    const int64_t PW = (int64_t)H * pitch;
+    const int64_t o = (int64_t)r * pitch + (c >> 5);
+    const int64_t j = (int64_t)r * W + c;
+    out[j] = (uint8_t)((planes[o] >> (c & 31)) & 1u);
+    out[(int64_t)H * W + j] = (uint8_t)((planes[PW + o] >> (c & 31)) & 1u);
+}
+
+__global__ void __launch_bounds__(256)
+k_flags_init(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job,
+             int32_t ntiles, int32_t parity, int32_t TR, int32_t TC) {
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= ntiles) return;
+    const DevScen& J = jobs[tile_job[g]];
+    const int lt = g - J.tile0;
+    const int trow = lt / J.tiles_c, tcol = lt - trow * J.tiles_c;
+    const uint32_t* p = J.planes[parity];
+    uint32_t any = 0;
+    for (int r = trow * TR; r < min(J.H, trow * TR + TR); ++r)
+        for (int w = tcol * TC; w < min(J.pitch, tcol * TC + TC); ++w)
+            any |= p[(int64_t)r * J.pitch + w];
+    J.flags[parity][lt] = any ? 1 : 0;   // other buffer not known to match
+}
+
+__global__ void __launch_bounds__(256)
+k_pignite(const DevScen* __restrict__ job, int32_t parity, float* __restrict__ out) {
+    const DevScen& J = *job;
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= J.W) return;
+    const int64_t j = (int64_t)r * J.W + c;
+    const int pitch = J.pitch;
+    const uint32_t* B = J.planes[parity];
+    const uint32_t* D = B + (int64_t)J.H * pitch;
+    auto bit = [&](const uint32_t* p, int rr, int cc) -> bool {
+        if (rr < 0 || rr >= J.H || cc < 0 || cc >= J.W) return false;
+        return (p[(int64_t)rr * pitch + (cc >> 5)] >> (cc & 31)) & 1u;
+    };
+    float P = 0.f;
+    const bool fuel = (J.fuel[(int64_t)r * pitch + (c >> 5)] >> (c & 31)) & 1u;
+    if (fuel && !bit(B, r, c) && !bit(D, r, c)) {
+        auto nb = [&](int dr, int dc) -> bool { return bit(B, r + dr, c + dc); };
+        float g[4];
+        P = cell_pignite<false>(J, j, nb, g);
+    }
+    out[j] = P;
+}
+
+__global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Deterministic per-scenario sum of the per-tile partials of the adjoint:
+// one work-group per scenario, fixed lane striding and a fixed tree.
+__global__ void __launch_bounds__(256)
+k_grad_reduce(const double* __restrict__ gpart, const int32_t* __restrict__ ranges,
+              double* __restrict__ grad) {
+    const int s = blockIdx.x;
+    const int a = ranges[s], b = ranges[s + 1];
+    __shared__ double sh[256 * 4];
+    double v[4] = {0, 0, 0, 0};
+    for (int g = a + threadIdx.x; g < b; g += 256)
+        for (int m = 0; m < 4; ++m) v[m] += gpart[(int64_t)g * 4 + m];
+    for (int m = 0; m < 4; ++m) sh[threadIdx.x * 4 + m] = v[m];
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d)
+            for (int m = 0; m < 4; ++m) sh[threadIdx.x * 4 + m] += sh[(threadIdx.x + d) * 4 + m];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) grad[s * 4 + threadIdx.x] = sh[threadIdx.x];
+}
+
+// --------------------------------------------------------------- Eq. 10
+
+// Bounding box of (yhat != 0) | (y != 0): box = {rmin, rmax, cmin, cmax}.
+__global__ void __launch_bounds__(256)
+k_loss_box(int32_t H, int32_t W, const float* __restrict__ yhat, const uint8_t* __restrict__ y,
+           int* __restrict__ box) {
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    bool nz = false;
+    if (c < W) {
+        const int64_t j = (int64_t)r * W + c;
+        nz = yhat[j] != 0.f || y[j] != 0;
+    }
+    const unsigned long long m = __ballot(nz);
+    if ((threadIdx.x & 63) == 0 && m) {
+        const int cbase = blockIdx.x * 256 + (threadIdx.x & ~63);
+        atomicMin(&box[0], r);
+        atomicMax(&box[1], r);
+        atomicMin(&box[2], cbase + (__ffsll((long long)m) - 1));
+        atomicMax(&box[3], cbase + 63 - (__clzll((long long)m)));
+    }
+}
+
+// BCE-with-logits over the crop (kind 0/1) and/or the 4x4 pool MSE (kind
+// 1/2).  Writes lambda = dL/dyhat and per-block FP64 partial sums
+// part[block] = (bce_sum, mse_sum); one block per 4 rows (a pool row).
+__global__ void __launch_bounds__(256)
+k_loss_terms(int32_t H, int32_t W, const float* __restrict__ yhat, const uint8_t* __restrict__ y,
+             int32_t kind, const int* __restrict__ box, float* __restrict__ lambda,
+             double* __restrict__ part) {
+    const int pr = blockIdx.x;  // rows 4 pr .. 4 pr + 3
+    const int b0 = box[0], b1 = box[1], c0 = box[2], c1 = box[3];
+    const bool has_box = b1 >= b0;
+    const double N = has_box ? (double)(b1 - b0 + 1) * (double)(c1 - c0 + 1) : 1.0;
+    const int Hp = H / 4, Wp = W / 4;
+    const double Np = (double)Hp * (double)Wp;
+    double bce = 0.0, mse = 0.0;
+    for (int r = 4 * pr; r < min(H, 4 * pr + 4); ++r)
+        for (int c = threadIdx.x; c < W; c += 256) {
+            const int64_t j = (int64_t)r * W + c;
+            double lam = 0.0;
+            if ((kind == 0 || kind == 1) && has_box && r >= b0 && r <= b1 && c >= c0 && c <= c1) {
+                const double z = (double)yhat[j], yy = (double)y[j];
+                const double sig = 1.0 / (1.0 + exp(-z));
+                bce += -(yy * log(sig) + (1.0 - yy) * log(1.0 - sig));
+                lam += (sig - yy) / N;
+            }
+            lambda[j] = (float)lam;
+        }
+    __syncthreads();
+    if ((kind == 1 || kind == 2) && pr < Hp) {
+        for (int pc = threadIdx.x; pc < Wp; pc += 256) {
+            double a = 0.0, b = 0.0;
+            for (int dr = 0; dr < 4; ++dr)
+                for (int dc = 0; dc < 4; ++dc) {
+                    const int64_t j = (int64_t)(4 * pr + dr) * W + 4 * pc + dc;
+                    a += (double)yhat[j];
+                    b += (double)y[j];
+                }
+            const double d = a / 16.0 - b / 16.0;
+            mse += d * d;
+            const float add = (float)(2.0 * d / (16.0 * Np));
+            for (int dr = 0; dr < 4; ++dr)
+                for (int dc = 0; dc < 4; ++dc) {
+                    const int64_t j = (int64_t)(4 * pr + dr) * W + 4 * pc + dc;
+                    lambda[j] = lambda[j] + add;
+                }
+        }
+    }
+    __shared__ double sh[2][256];
+    sh[0][threadIdx.x] = bce;
+    sh[1][threadIdx.x] = mse;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + d];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * pr] = sh[0][0];
+        part[2 * pr + 1] = sh[1][0];
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_loss_final(int32_t H, int32_t W, int32_t kind, const int* __restrict__ box,
+             const double* __restrict__ part, int32_t nparts, double* __restrict__ loss) {
+    __shared__ double sh[2][256];
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + d];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + d];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double L = 0.0;
+        if ((kind == 0 || kind == 1) && box[1] >= box[0])
+            L += sh[0][0] / ((double)(box[1] - box[0] + 1) * (double)(box[3] - box[2] + 1));
+        const double Np = (double)(H / 4) * (double)(W / 4);
+        if ((kind == 1 || kind == 2) && Np > 0) L += sh[1][0] / Np;
+        *loss = L;
+    }
+}
+
+__global__ void k_box_init(int* box, int32_t H, int32_t W) {
+    box[0] = H;
+    box[1] = -1;
+    box[2] = W;
+    box[3] = -1;
+}
+
+// ------------------------------------------------- checkpoints, parameters
+
+__global__ void __launch_bounds__(256)
+k_ckpt_save(const DevScen* __restrict__ jobs, int32_t parity, int32_t slot) {
+    const DevScen& J = jobs[blockIdx.y];
+    const int64_t nw = 2 * (int64_t)J.H * J.pitch;
+    const uint32_t* src = J.planes[parity];
+    uint32_t* dst = J.ckpt + (int64_t)slot * nw;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nw; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[i];
+}
+
+__global__ void __launch_bounds__(256)
+k_ckpt_load(const DevScen* __restrict__ jobs) {
+    const DevScen& J = jobs[blockIdx.y];
+    const int64_t nw = 2 * (int64_t)J.H * J.pitch;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nw; i += (int64_t)gridDim.x * 256)
+        J.planes[0][i] = J.ckpt[i];
+}
+
+__global__ void k_set_params(DevScen* jobs, ParamBlock pb) {
+    const int i = threadIdx.x;
+    if (i < pb.count) {
+        DevScen& J = jobs[pb.first + i];
+        J.p_h = pb.v[i][0];
+        J.a = pb.v[i][1];
+        J.c1 = pb.v[i][2];
+        J.c2 = pb.v[i][3];
+        J.p_continue = pb.v[i][4];
+    }
+}
+
+__global__ void k_set_seeds(DevScen* jobs, SeedBlock sb) {
+    const int i = threadIdx.x;
+    if (i < sb.count) {
+        jobs[sb.first + i].seed_lo = sb.lo[i];
+        jobs[sb.first + i].seed_hi = sb.hi[i];
+    }
+}
+
+// --------------------------------------------------------------- launchers
+
+hipError_t launch_ckpt_save(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
+                            int32_t slot, int64_t max_words) {
+    if (n <= 0) return hipSuccess;
+    const unsigned gx = (unsigned)std::min<int64_t>((2 * max_words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_ckpt_save, dim3(gx, n), dim3(256), 0, st, d_jobs, parity, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_ckpt_load(hipStream_t st, const DevScen* d_jobs, int32_t n, int64_t max_words) {
+    if (n <= 0) return hipSuccess;
+    const unsigned gx = (unsigned)std::min<int64_t>((2 * max_words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_ckpt_load, dim3(gx, n), dim3(256), 0, st, d_jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_params(hipStream_t st, DevScen* d_jobs, const ParamBlock& pb) {
+    hipLaunchKernelGGL(k_set_params, dim3(1), dim3(64), 0, st, d_jobs, pb);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_seeds(hipStream_t st, DevScen* d_jobs, const SeedBlock& sb) {
+    hipLaunchKernelGGL(k_set_seeds, dim3(1), dim3(64), 0, st, d_jobs, sb);
+    return hipGetLastError();
+}
+
+namespace {
+inline dim3 cell_grid(int H, int cols) { return dim3((cols + 255) / 256, H); }
+}  // namespace
+
+hipError_t launch_prologue(hipStream_t st, const DevScen* /*d_job*/, const DevScen& J,
+                           const float* p_veg, const float* p_den, const float* ws,
+                           const float* wd, float ws0, float wd0, const uint8_t* ign,
+                           float4* rec, uint32_t* fuel, float* yhat, int* d_err) {
+    hipLaunchKernelGGL(k_prologue, cell_grid(J.H, J.pitch * 32), dim3(256), 0, st, J.H, J.W,
+                       J.pitch, p_veg, p_den, J.elev, ws, wd, ws0, wd0, ign, rec, fuel,
+                       J.planes[0], yhat, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(hipStream_t st, const DevScen& J, const uint8_t* ign,
+                             uint32_t* planes, float* yhat) {
+    hipLaunchKernelGGL(k_init_state, cell_grid(J.H, J.pitch * 32), dim3(256), 0, st, J.H, J.W,
+                       J.pitch, ign, planes, yhat);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_state(hipStream_t st, const DevScen& J, const uint8_t* in,
+                            uint32_t* planes, int* d_err) {
+    hipLaunchKernelGGL(k_set_state, cell_grid(J.H, J.pitch * 32), dim3(256), 0, st, J.H, J.W,
+                       J.pitch, in, planes, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_state(hipStream_t st, const DevScen& J, const uint32_t* planes,
+                            uint8_t* out) {
+    hipLaunchKernelGGL(k_get_state, cell_grid(J.H, J.W), dim3(256), 0, st, J.H, J.W, J.pitch,
+                       planes, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags_init(hipStream_t st, const DevScen* d_jobs, const int32_t* d_tile_job,
+                             int32_t ntiles, int32_t parity, TileShape sh) {
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flags_init, dim3((ntiles + 255) / 256), dim3(256), 0, st, d_jobs,
+                       d_tile_job, ntiles, parity, sh.tr, sh.tc);
+    return hipGetLastError();
+}
+
+hipError_t launch_pignite(hipStream_t st, const DevScen* d_job, const DevScen& J,
+                          int32_t parity, float* out) {
+    hipLaunchKernelGGL(k_pignite, cell_grid(J.H, J.W), dim3(256), 0, st, d_job, parity, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, size_t n, uint32_t v) {
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_reduce(hipStream_t st, const double* gpart, const int32_t* d_ranges,
+                              int32_t n, double* grad) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_reduce, dim3(n), dim3(256), 0, st, gpart, d_ranges, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(hipStream_t st, int32_t H, int32_t W, const float* yhat,
+                       const uint8_t* y, int32_t kind, float* lambda, int* d_box,
+                       double* d_part, double* loss_out) {
+    const int nparts = (H + 3) / 4;
+    hipLaunchKernelGGL(k_box_init, dim3(1), dim3(1), 0, st, d_box, H, W);
+    hipLaunchKernelGGL(k_loss_box, cell_grid(H, W), dim3(256), 0, st, H, W, yhat, y, d_box);
+    hipLaunchKernelGGL(k_loss_terms, dim3(nparts), dim3(256), 0, st, H, W, yhat, y, kind, d_box,
+                       lambda, d_part);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, H, W, kind, d_box, d_part,
+                       nparts, loss_out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- step shape dispatch table
+
+namespace {
+using StepFn = void (*)(const DevScen*, const int32_t*, int32_t, int32_t, int32_t, int32_t,
+                        int32_t, const float*, unsigned long long*);
+
+struct StepEntry {
+    int tr, tc, km;
+    bool adj;
+    StepFn fn;
+};
+
+#define FS_SHAPE(TR, TC, KM)                          \
+    {TR, TC, KM, false, &k_step<TR, TC, KM, false>}, \
+    {TR, TC, KM, true, &k_step<TR, TC, KM, true>},
+
+const StepEntry kSteps[] = {
+    FS_SHAPE(16, 4, 1) FS_SHAPE(16, 4, 4) FS_SHAPE(16, 4, 8) FS_SHAPE(16, 4, 16)
+    FS_SHAPE(16, 8, 1) FS_SHAPE(16, 8, 4) FS_SHAPE(16, 8, 8) FS_SHAPE(16, 8, 16)
+    FS_SHAPE(32, 4, 1) FS_SHAPE(32, 4, 8) FS_SHAPE(32, 4, 16)
+    FS_SHAPE(32, 8, 1) FS_SHAPE(32, 8, 8) FS_SHAPE(32, 8, 16)
+    FS_SHAPE(8, 16, 1) FS_SHAPE(8, 16, 4) FS_SHAPE(8, 16, 8)
+};
+#undef FS_SHAPE
+
+const StepEntry* find_step(TileShape sh, bool adj) {
+    for (const auto& e : kSteps)
+        if (e.tr == sh.tr && e.tc == sh.tc && e.km == sh.km && e.adj == adj) return &e;
+    return nullptr;
+}
+}  // namespace
+
+bool step_shape_supported(TileShape sh, bool adj) { return find_step(sh, adj) != nullptr; }
+
+hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_jobs,
+                       const int32_t* d_tile_job, int32_t ntiles, int32_t parity,
+                       int32_t t_off, int32_t ksteps, int32_t skip, const float* lam,
+                       unsigned long long* d_stats) {
+    const StepEntry* e = find_step(sh, adj);
+    if (!e) return hipErrorInvalidValue;
+    if (ntiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(e->fn, dim3(ntiles), dim3(256), 0, st, d_jobs, d_tile_job, ntiles,
+                       parity, t_off, ksteps, skip, lam, d_stats);
+    return hipGetLastError();
+}
+
+}  // namespace fs

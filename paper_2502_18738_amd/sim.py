@@ -1,0 +1,196 @@
+"""Python handle over libfiresim (argument marshalling only).
+
+PyTorch provides device memory and the stream; every step of the automaton
+runs in the library's HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import SimError
+
+
+def _dev_tensor(a, dtype, device):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        t = a.to(device=device, dtype=dtype)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
+    return t.contiguous()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Sim:
+    """n wildfire scenarios advanced together on one GPU.
+
+    ``scenarios``: objects with H, W, cell_m, seed, scenario_id, the fields
+    p_veg, p_den, elevation, wind_speed, wind_dir (or None with the
+    ``*_scalar`` values), init_burning and the parameters p_h, a, c1, c2,
+    p_continue (numpy arrays or torch tensors).
+    """
+
+    def __init__(self, scenarios: Sequence, *, device="cuda", calib: bool = False,
+                 stats: bool = False, ckpt_every: int = 20, T_max: Optional[int] = None,
+                 exec: Optional[dict] = None, stream: Optional[torch.cuda.Stream] = None):
+        self._lib = _abi.load()
+        self.device = torch.device(device)
+        self.n = len(scenarios)
+        self.shapes = [(int(s.H), int(s.W)) for s in scenarios]
+        self.offsets = np.concatenate([[0], np.cumsum([h * w for h, w in self.shapes])])
+        self.calib = bool(calib)
+        flags = (_abi.SIM_F_CALIB if calib else 0) | (_abi.SIM_F_STATS if stats else 0)
+        if calib and T_max is None:
+            T_max = max(int(getattr(s, "T", 0)) for s in scenarios)
+        T_max = int(T_max or 0)
+        self._keep = []
+        descs = (_abi.sim_desc * self.n)()
+        for i, s in enumerate(scenarios):
+            f32 = lambda a: _dev_tensor(a, torch.float32, self.device)
+            pv, pd, el = f32(s.p_veg), f32(s.p_den), f32(s.elevation)
+            ws, wd = f32(s.wind_speed), f32(s.wind_dir)
+            ign = _dev_tensor(s.init_burning, torch.uint8, self.device)
+            self._keep += [pv, pd, el, ws, wd, ign]
+            fields = _abi.sim_fields(
+                pv.data_ptr(), pd.data_ptr(), el.data_ptr(),
+                None if ws is None else ws.data_ptr(), None if wd is None else wd.data_ptr(),
+                float(s.wind_speed_scalar), float(s.wind_dir_scalar), ign.data_ptr())
+            par = _abi.sim_params(*(float(np.float32(getattr(s, k)))
+                                    for k in ("p_h", "a", "c1", "c2", "p_continue")))
+            descs[i] = _abi.sim_desc(int(s.H), int(s.W), float(s.cell_m),
+                                     int(s.scenario_id) & 0xFFFFFFFF,
+                                     int(s.seed) & 0xFFFFFFFFFFFFFFFF, par, fields)
+        self._descs = descs
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = self._lib.sim_workspace_size(descs, self.n, flags, int(ckpt_every), T_max)
+        if nbytes == 0:
+            raise SimError(_abi.SIM_E_ARG, "invalid scenario descriptions")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        h = ctypes.c_void_p()
+        rc = self._lib.sim_init(ctypes.byref(h), descs, self.n, ctypes.c_void_p(aligned), nbytes,
+                                ctypes.c_void_p(self.stream.cuda_stream), flags,
+                                int(ckpt_every), T_max)
+        if rc != 0:
+            raise SimError(rc, self._lib.sim_last_error(None).decode())
+        self._h = h
+        if exec is not None:
+            self.set_exec(**exec)
+
+    # ------------------------------------------------------------ plumbing
+    def _check(self, rc):
+        if rc != 0:
+            raise SimError(rc, self._lib.sim_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --------------------------------------------------------------- calls
+    def set_exec(self, tile_rows=16, tile_words=8, depth=8, skip=True):
+        e = _abi.sim_exec(int(tile_rows), int(tile_words), int(depth), int(bool(skip)))
+        self._check(self._lib.sim_set_exec(self._h, ctypes.byref(e)))
+
+    def get_exec(self):
+        e = _abi.sim_exec()
+        self._check(self._lib.sim_get_exec(self._h, ctypes.byref(e)))
+        return dict(tile_rows=e.tile_rows, tile_words=e.tile_words, depth=e.depth,
+                    skip=bool(e.skip))
+
+    def run(self, T: int):
+        self._check(self._lib.sim_run(self._h, int(T)))
+
+    def step(self):
+        self._check(self._lib.sim_step(self._h))
+
+    @property
+    def t(self) -> int:
+        v = ctypes.c_int32()
+        self._check(self._lib.sim_get_step(self._h, ctypes.byref(v)))
+        return v.value
+
+    def set_params(self, params: Iterable):
+        """params: n rows of (p_h, a, c1, c2, p_continue)."""
+        rows = [tuple(float(x) for x in r) for r in params]
+        arr = (_abi.sim_params * self.n)(*[_abi.sim_params(*r) for r in rows])
+        self._check(self._lib.sim_set_params(self._h, arr))
+
+    def reset(self, seeds: Optional[Sequence[int]] = None):
+        if seeds is None:
+            self._check(self._lib.sim_reset(self._h, None))
+        else:
+            arr = (ctypes.c_uint64 * self.n)(*[int(x) & 0xFFFFFFFFFFFFFFFF for x in seeds])
+            self._check(self._lib.sim_reset(self._h, arr))
+
+    def get_state(self, s: int = 0) -> torch.Tensor:
+        H, W = self.shapes[s]
+        out = torch.empty((2, H, W), dtype=torch.uint8, device=self.device)
+        self._check(self._lib.sim_get_state(self._h, s, _ptr(out)))
+        return out
+
+    def set_state(self, s: int, planes, step: int):
+        H, W = self.shapes[s]
+        t = _dev_tensor(planes, torch.uint8, self.device)
+        if tuple(t.shape) != (2, H, W):
+            raise ValueError(f"state must be 2 x {H} x {W}")
+        self._check(self._lib.sim_set_state(self._h, s, _ptr(t), int(step)))
+        self.stream.synchronize()
+
+    def pignite(self, s: int = 0) -> torch.Tensor:
+        H, W = self.shapes[s]
+        out = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        self._check(self._lib.sim_pignite(self._h, s, _ptr(out)))
+        return out
+
+    def accumulator(self, s: int = 0) -> torch.Tensor:
+        H, W = self.shapes[s]
+        out = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        self._check(self._lib.sim_accumulator(self._h, s, _ptr(out)))
+        return out
+
+    def accumulators(self) -> torch.Tensor:
+        """All accumulators concatenated (flat FP32, the adjoint's layout)."""
+        out = torch.empty(int(self.offsets[-1]), dtype=torch.float32, device=self.device)
+        for s in range(self.n):
+            a, b = int(self.offsets[s]), int(self.offsets[s + 1])
+            self._check(self._lib.sim_accumulator(self._h, s, _ptr(out[a:b])))
+        return out
+
+    def adjoint(self, dL_dyhat: torch.Tensor) -> torch.Tensor:
+        lam = dL_dyhat.to(device=self.device, dtype=torch.float32).contiguous().view(-1)
+        if lam.numel() != int(self.offsets[-1]):
+            raise ValueError("dL_dyhat must hold every scenario's grid, concatenated")
+        grad = torch.empty((self.n, 4), dtype=torch.float64, device=self.device)
+        self._check(self._lib.sim_adjoint(self._h, _ptr(lam), _ptr(grad)))
+        return grad
+
+    def loss_grad(self, target, kind: int = _abi.SIM_LOSS_BCE):
+        y = _dev_tensor(target, torch.uint8, self.device).view(-1)
+        if y.numel() != int(self.offsets[-1]):
+            raise ValueError("target must hold every scenario's grid, concatenated")
+        loss = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        grad = torch.empty((self.n, 4), dtype=torch.float64, device=self.device)
+        self._check(self._lib.sim_loss_grad(self._h, _ptr(y), int(kind), _ptr(loss), _ptr(grad)))
+        return loss, grad
+
+    def stats(self) -> dict:
+        v = (ctypes.c_uint64 * 4)()
+        self._check(self._lib.sim_stats(self._h, v))
+        return dict(tiles=int(v[0]), trials=int(v[1]), ties=int(v[2]), launches=int(v[3]))

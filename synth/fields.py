@@ -7,8 +7,9 @@ from ``numpy.random.default_rng(seed)`` with a fixed draw order:
 1. vegetation class, 2. density class, 3. non-burnable mask, 4. elevation
 noise, 5. wind-speed noise, 6. wind-direction noise, 7. ignition positions.
 
-Smoothing is ``scipy.ndimage.gaussian_filter`` (mode ``reflect``), smoothed
-fields are min-max scaled, non-burnable cells get ``p_veg = -1`` (the paper's
+Smoothing is a Gaussian applied in the Fourier domain (periodic boundary;
+``scipy.ndimage.fourier_gaussian`` on a real FFT), smoothed fields are
+min-max scaled, non-burnable cells get ``p_veg = -1`` (the paper's
 "very small p_veg" reading of the no-fuel state, Sec. 2.2), and ignition cells
 are forced burnable.  Grid orientation: row 0 is north, rows run south,
 columns run east.  Wind direction is the heading the wind blows toward, in
@@ -23,7 +24,8 @@ import dataclasses
 from typing import Optional
 
 import numpy as np
-from scipy.ndimage import gaussian_filter
+import scipy.fft
+from scipy.ndimage import fourier_gaussian, gaussian_filter
 
 # Vegetation and density class -> scaling factor (the workload definitions).
 VEG_CLASSES = np.array([-0.3, 0.0, 0.4, 0.2], dtype=np.float32)
@@ -98,7 +100,9 @@ def _minmax(x, lo, hi):
 
 
 def _smooth(rng, H, W, sigma):
-    return gaussian_filter(rng.standard_normal((H, W)), sigma=sigma, mode="reflect")
+    x = rng.standard_normal((H, W))
+    f = fourier_gaussian(scipy.fft.rfft2(x, workers=-1), sigma=sigma, n=W)
+    return scipy.fft.irfft2(f, s=(H, W), workers=-1)
 
 
 def _base(rng, H, W, nonburn, nonburn_frac, e_sigma, e_max):
