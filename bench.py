@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # state, F = (1+p_veg)(1+p_den), elevation, wind speed and direction, and
 # writes 2 bits): 0.5 + 4 + 4 + 8.
 DENSE_BYTES_PER_CELL_STEP = 16.5
-DEFAULT_EXEC = dict(tile_rows=16, tile_words=8, depth=8, skip=True)
+DEFAULT_EXEC = dict(tile_rows=16, tile_words=4, depth=16, skip=True)
 PLAIN_EXEC = dict(tile_rows=16, tile_words=8, depth=1, skip=False)
 
 
@@ -86,6 +86,11 @@ def leg_main(args, torch, Sim, synth):
     s = synth.config2()
     T = s.T
     sim = Sim([s], exec=DEFAULT_EXEC)
+    if args.autotune:
+        # tune on a mid-run state (the fire front at 400 steps), then restart
+        sim.run(400)
+        DEFAULT_EXEC.update(sim.autotune(32))
+        log("autotuned shape:", DEFAULT_EXEC)
     launches_per_run = -(-T // DEFAULT_EXEC["depth"])
 
     def run():
@@ -104,7 +109,8 @@ def leg_main(args, torch, Sim, synth):
     roof = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 3), "traffic": None,
-        "kernel": "k_step<16,8,8,false>", "launch_us": round(launch_s * 1e6, 2),
+        "kernel": "k_step<{tile_rows},{tile_words},{depth},false>".format(**DEFAULT_EXEC),
+        "launch_us": round(launch_s * 1e6, 2),
         "basis": "effective: dense-formulation bytes (16.5 B per cell-step) x cell-steps "
                  "per launch; the kernel reads fields only for cells with a trial",
     }
@@ -242,12 +248,34 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--legs", default="main,plain,calib,batched,cpu")
+    ap.add_argument("--exec", default=None, metavar="TR,TC,DEPTH,SKIP",
+                    help="execution shape of the main leg (tile rows, tile words, steps "
+                         "per launch, skip 0/1)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default (or --exec) shape instead of autotuning")
+    ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (reference "
+                         "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_ref:
+        import torch
+        a = torch.empty(args.copy_ref // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": args.copy_ref}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
               "decomposition is not built", file=sys.stderr)
         sys.exit(2)
     legs = set(args.legs.split(","))
+    if args.exec:
+        tr, tc, dp, sk = (int(x) for x in args.exec.split(","))
+        DEFAULT_EXEC.update(tile_rows=tr, tile_words=tc, depth=dp, skip=bool(sk))
+        args.autotune = False
 
     import torch
     import synth

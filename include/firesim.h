@@ -130,11 +130,24 @@ SIM_API int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* w
              size_t ws_bytes, void* stream, uint32_t flags, int32_t ckpt_every,
              int32_t T_max);
 
-/* Choose the execution shape (defaults: an autotuned shape, or 16 x 8 words,
- * depth 8, skip on).  Only whitelisted shapes are compiled; others give
+/* Choose the execution shape (default: 16 rows x 4 words, depth 16, skip on;
+ * sim_autotune picks one by timing).  Only whitelisted shapes are compiled; others give
  * SIM_E_SHAPE. */
 SIM_API int sim_set_exec(sim_handle* h, const sim_exec* e);
 SIM_API int sim_get_exec(const sim_handle* h, sim_exec* e);
+
+/* Autotuner: times every compiled execution shape (temporal depth = the
+ * shape's halo, skipping on) over T_probe steps from the current state, keeps
+ * the fastest and writes it to *best (nullable).  The state and step counter
+ * are restored afterwards, so results do not depend on having tuned.  Waits
+ * for the stream.  Not available in calibration mode (SIM_E_STATE). */
+SIM_API int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best);
+
+/* Replay each distinct launch sequence of sim_run (same start step, parity,
+ * T and shape) as one captured HIP graph (on by default; 0 turns it off and
+ * frees the captured graphs).  Falls back to direct launches if capture is
+ * not possible. */
+SIM_API int sim_use_graphs(sim_handle* h, int32_t on);
 
 /* Advance every scenario by T >= 0 steps (Sec. 2.2 transition rules).  In
  * calibration mode the accumulator records p_ignite at each ignition and the

@@ -60,7 +60,7 @@ EXPORTS = (
     "sim_workspace_size", "sim_init", "sim_set_exec", "sim_get_exec", "sim_run", "sim_step",
     "sim_get_step", "sim_set_params", "sim_reset", "sim_get_state", "sim_set_state",
     "sim_pignite", "sim_accumulator", "sim_adjoint", "sim_loss_grad", "sim_stats",
-    "sim_last_error", "sim_destroy", "sim_version",
+    "sim_last_error", "sim_destroy", "sim_version", "sim_autotune", "sim_use_graphs",
 )
 
 _lib = None
@@ -71,6 +71,9 @@ def load():
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that the library binds to the runtime that owns torch's streams and memory
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2502_18738_amd.build` "
@@ -99,6 +102,8 @@ def load():
         "sim_last_error": (ctypes.c_char_p, [H]),
         "sim_destroy": (None, [H]),
         "sim_version": (ctypes.c_char_p, []),
+        "sim_autotune": (ctypes.c_int, [H, i32, ctypes.POINTER(sim_exec)]),
+        "sim_use_graphs": (ctypes.c_int, [H, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

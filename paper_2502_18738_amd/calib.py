@@ -1,0 +1,92 @@
+"""Calibration of (p_h, a, c1, c2) with the hand-written adjoint.
+
+``FireCalib`` is a ``torch.autograd.Function``: its forward runs the CA in
+calibration mode on the GPU and returns the accumulator y-hat (p_ignite at each
+cell's ignition step, Sec. 2.2 data flow); its backward calls the library's
+adjoint, which recomputes every checkpoint segment and returns
+d(sum lambda * y-hat)/d theta with the sampled states held constant (Sec. 2.3).
+
+``calibrate`` is the gradient-descent loop of Algorithm 1 for one observation
+per epoch: a fresh seed per epoch (the epoch seed), forward, Eq. 10 loss and
+its gradient (fused in the library), AdamW (lr 5e-3 by default, Sec. 2.3) and
+the parameter clamps of Algorithm 1.
+"""
+
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+import torch
+
+from ._abi import SIM_LOSS_BCE
+from .sim import Sim
+
+# Clamp ranges of Algorithm 1: p_h in [0.2, 1], a, c1, c2 in [0, 1].
+CLAMP_LO = (0.2, 0.0, 0.0, 0.0)
+CLAMP_HI = (1.0, 1.0, 1.0, 1.0)
+
+
+class FireCalib(torch.autograd.Function):
+    """y-hat = FireCalib.apply(theta, sim, T, seeds).
+
+    theta: (n, 4) tensor of (p_h, a, c1, c2) per scenario.  Returns the
+    accumulators of all scenarios concatenated (flat FP32).  p_continue is
+    taken from ``sim.p_continue`` and never differentiated.
+    """
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, sim: Sim, T: int, seeds: Optional[Sequence[int]]):
+        if not sim.calib:
+            raise ValueError("FireCalib needs a Sim created with calib=True")
+        p = theta.detach().to("cpu", torch.float32)
+        rows = [tuple(r) + (pc,) for r, pc in zip(p.tolist(), sim.p_continue)]
+        sim.set_params(rows)
+        sim.reset(seeds)
+        sim.run(int(T))
+        ctx.sim = sim
+        ctx.theta_dtype = theta.dtype
+        return sim.accumulators()
+
+    @staticmethod
+    def backward(ctx, grad_yhat):
+        g = ctx.sim.adjoint(grad_yhat.contiguous())
+        return g.to(ctx.theta_dtype), None, None, None
+
+
+def clamp_(theta: torch.Tensor) -> torch.Tensor:
+    lo = torch.tensor(CLAMP_LO, dtype=theta.dtype, device=theta.device)
+    hi = torch.tensor(CLAMP_HI, dtype=theta.dtype, device=theta.device)
+    with torch.no_grad():
+        theta.copy_(torch.maximum(torch.minimum(theta, hi), lo))
+    return theta
+
+
+def calibrate(sim: Sim, target, theta0, *, T: int, steps: int = 50, lr: float = 5e-3,
+              loss_kind: int = SIM_LOSS_BCE, seed0: int = 1000, callback=None):
+    """Gradient-descent calibration of every scenario of ``sim`` against
+    ``target`` (uint8, the n grids concatenated).
+
+    Returns (theta, history) where history holds (loss per scenario, theta)
+    after every step.  Gradient step g uses Philox seed ``seed0 + g`` for all
+    scenarios (a new epoch seed each step).
+    """
+    theta = torch.as_tensor(theta0, dtype=torch.float32, device=sim.device).clone()
+    theta.requires_grad_(True)
+    opt = torch.optim.AdamW([theta], lr=lr)
+    history = []
+    y = torch.as_tensor(target, device=sim.device).to(torch.uint8).view(-1)
+    for g in range(steps):
+        p = theta.detach().to("cpu")
+        rows = [tuple(r) + (pc,) for r, pc in zip(p.tolist(), sim.p_continue)]
+        sim.set_params(rows)
+        sim.reset([seed0 + g] * sim.n)
+        sim.run(int(T))
+        loss, grad = sim.loss_grad(y, loss_kind)
+        theta.grad = grad.to(theta.dtype)
+        opt.step()
+        opt.zero_grad(set_to_none=True)
+        clamp_(theta)
+        history.append((loss.detach().cpu(), theta.detach().cpu().clone()))
+        if callback is not None:
+            callback(g, loss, theta)
+    return theta.detach(), history

@@ -18,7 +18,7 @@
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMinTR = 8, kMinTC = 4;  // smallest whitelisted tile -> flag capacity
+constexpr int kMinTR = 8, kMinTC = 2;  // smallest whitelisted tile -> flag capacity
 constexpr int kMaxN = 65536;
 constexpr int kMaxSide = 1 << 16;
 const float kC = 1.1486328125f;        // f_p constant of Eq. 5 / 8, FP32
@@ -32,7 +32,7 @@ struct ScenLayout {
     int32_t pitch;
     int64_t PW;          // words per bit-plane
     int64_t max_tiles;   // flag capacity
-    size_t rec, fuel, planes[2], flags[2], yhat, ckpt;
+    size_t rec, fuel, planes[2], flags[2], yhat, ckpt, tune;
 };
 
 struct Layout {
@@ -80,7 +80,8 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         s.planes[1] = take(8 * (size_t)s.PW);
         s.flags[0] = take((size_t)s.max_tiles);
         s.flags[1] = take((size_t)s.max_tiles);
-        s.yhat = s.ckpt = 0;
+        s.yhat = s.ckpt = s.tune = 0;
+        if (!calib) s.tune = take(8 * (size_t)s.PW);   // state saved while autotuning
         if (calib) {
             s.yhat = take(4 * (size_t)cells);
             s.ckpt = take(8 * (size_t)s.PW * (size_t)L->nseg);
@@ -187,6 +188,24 @@ struct sim_handle {
     unsigned long long launches = 0;
     int64_t max_words = 0;
     std::string err;
+    // captured launch sequences of sim_run, keyed by where they start
+    struct Graph {
+        int step, T, parity, ntiles;
+        sim_exec ex;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    bool use_graphs = true;
+    hipStream_t cap = nullptr;      // private stream used only for capture
+
+    void drop_graphs() {
+        for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
+    ~sim_handle() {
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
 
     fs::DevScen* d_jobs() { return reinterpret_cast<fs::DevScen*>(ws + L.jobs); }
     int32_t* d_tile_job() { return reinterpret_cast<int32_t*>(ws + L.tile_job); }
@@ -233,6 +252,7 @@ int rebuild_tiles(sim_handle* h) {
     }
     h->ntiles = g;
     h->adj_T = -1;
+    h->drop_graphs();
     int rc = h->hip(hipMemcpyAsync(h->d_jobs(), h->job.data(), sizeof(fs::DevScen) * h->n,
                                    hipMemcpyHostToDevice, h->st), "upload jobs");
     if (rc) return rc;
@@ -329,7 +349,7 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
     // default execution shape
     int32_t max_pitch = 0;
     for (const auto& s : h->L.s) max_pitch = std::max(max_pitch, s.pitch);
-    h->ex = sim_exec{16, max_pitch <= 4 ? 4 : 8, 8, 1};
+    h->ex = sim_exec{16, max_pitch <= 2 ? 2 : 4, 16, 1};
     h->sh = shape_of(h->ex);
 
     h->job.resize(n);
@@ -428,29 +448,180 @@ int sim_get_exec(const sim_handle* h, sim_exec* e) {
     return SIM_OK;
 }
 
-int sim_run(sim_handle* h, int32_t T) {
-    if (!h) return SIM_E_ARG;
-    if (T < 0) return h->fail(SIM_E_SHAPE, "T must be >= 0");
-    if (h->calib() && (int64_t)h->step + T > h->T_max)
-        return h->fail(SIM_E_STATE, "calibration run would pass T_max = %d", h->T_max);
-    if ((int64_t)h->step + T > INT_MAX / 2) return h->fail(SIM_E_SHAPE, "step counter overflow");
-    unsigned long long* stats = (h->flags & SIM_F_STATS) ? h->d_stats() : nullptr;
+}  // extern "C"
+
+namespace {
+
+// Enqueue the launches of T steps on `st`, advancing the handle's counters.
+int enqueue_run(sim_handle* h, hipStream_t st, int T, unsigned long long* stats) {
     while (T > 0) {
         int k = std::min(h->ex.depth, T);
         if (h->calib()) k = std::min(k, h->ckpt_every - h->step % h->ckpt_every);
-        int rc = h->hip(fs::launch_step(h->st, h->sh, false, h->d_jobs(), h->d_tile_job(),
-                                        h->ntiles, h->parity, h->step, k, h->ex.skip, nullptr,
-                                        stats), "step kernel");
+        int rc = h->hip(fs::launch_step(st, h->sh, false, h->d_jobs(), h->d_tile_job(), h->ntiles,
+                                        h->parity, h->step, k, h->ex.skip, nullptr, stats),
+                        "step kernel");
         if (rc) return rc;
         ++h->launches;
         h->parity ^= 1;
         h->step += k;
         T -= k;
         if (h->calib() && h->step % h->ckpt_every == 0 && h->step < h->T_max) {
-            rc = save_ckpt(h, h->step / h->ckpt_every);
+            rc = h->hip(fs::launch_ckpt_save(st, h->d_jobs(), h->n, h->parity,
+                                             h->step / h->ckpt_every, h->max_words),
+                        "checkpoint");
             if (rc) return rc;
         }
     }
+    return SIM_OK;
+}
+
+bool same_exec(const sim_exec& a, const sim_exec& b) {
+    return a.tile_rows == b.tile_rows && a.tile_words == b.tile_words && a.depth == b.depth &&
+           a.skip == b.skip;
+}
+
+// Replay (or capture, then replay) the launch sequence of T steps from the
+// handle's current step and parity as one HIP graph on the handle's stream.
+// Returns SIM_E_STATE when capture is not possible (the caller then launches
+// directly).
+int run_graph(sim_handle* h, int T) {
+    for (auto& g : h->graphs) {
+        if (g.step == h->step && g.T == T && g.parity == h->parity && g.ntiles == h->ntiles &&
+            same_exec(g.ex, h->ex)) {
+            int rc = h->hip(hipGraphLaunch(g.exec, h->st), "graph launch");
+            if (rc) return rc;
+            // advance the counters exactly as the captured sequence did
+            int t = T, st = h->step, par = h->parity;
+            while (t > 0) {
+                int k = std::min(h->ex.depth, t);
+                if (h->calib()) k = std::min(k, h->ckpt_every - st % h->ckpt_every);
+                par ^= 1;
+                st += k;
+                t -= k;
+                ++h->launches;
+            }
+            h->step = st;
+            h->parity = par;
+            return SIM_OK;
+        }
+    }
+    if (!h->cap && hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess) {
+        h->cap = nullptr;
+        return SIM_E_STATE;
+    }
+    const int step0 = h->step, par0 = h->parity;
+    const unsigned long long l0 = h->launches;
+    if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return SIM_E_STATE;
+    int rc = enqueue_run(h, h->cap, T, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap, &graph);
+    hipGraphExec_t exec = nullptr;
+    if (!rc && e == hipSuccess && graph &&
+        hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        if (h->graphs.size() >= 8) {
+            (void)hipGraphExecDestroy(h->graphs.front().exec);
+            h->graphs.erase(h->graphs.begin());
+        }
+        h->graphs.push_back(sim_handle::Graph{step0, T, par0, h->ntiles, h->ex, exec});
+        return h->hip(hipGraphLaunch(exec, h->st), "graph launch");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    // capture failed: undo the counter updates, let the caller launch directly
+    h->step = step0;
+    h->parity = par0;
+    h->launches = l0;
+    h->use_graphs = false;
+    return SIM_E_STATE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_run(sim_handle* h, int32_t T) {
+    if (!h) return SIM_E_ARG;
+    if (T < 0) return h->fail(SIM_E_SHAPE, "T must be >= 0");
+    if (h->calib() && (int64_t)h->step + T > h->T_max)
+        return h->fail(SIM_E_STATE, "calibration run would pass T_max = %d", h->T_max);
+    if ((int64_t)h->step + T > INT_MAX / 2) return h->fail(SIM_E_SHAPE, "step counter overflow");
+    if (T == 0) return SIM_OK;
+    unsigned long long* stats = (h->flags & SIM_F_STATS) ? h->d_stats() : nullptr;
+    if (h->use_graphs && !stats && T > h->ex.depth) {
+        const int rc = run_graph(h, T);
+        if (rc != SIM_E_STATE) return rc;
+    }
+    return enqueue_run(h, h->st, T, stats);
+}
+
+int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best) {
+    if (!h) return SIM_E_ARG;
+    if (h->calib()) return h->fail(SIM_E_STATE, "sim_autotune is not available in calibration mode");
+    if (T_probe < 1 || T_probe > 4096) return h->fail(SIM_E_SHAPE, "T_probe must be in [1, 4096]");
+    fs::TileShape shapes[64];
+    const int ns = fs::step_shapes(shapes, 64);
+    const int step0 = h->step, par0 = h->parity;
+    const sim_exec ex0 = h->ex;
+    int rc = SIM_OK;
+    for (int i = 0; i < h->n && !rc; ++i)
+        rc = h->hip(hipMemcpyAsync(h->ws + h->L.s[i].tune, h->job[i].planes[par0],
+                                   8 * (size_t)h->L.s[i].PW, hipMemcpyDeviceToDevice, h->st),
+                    "save state");
+    if (rc) return rc;
+    auto restore = [&]() -> int {
+        for (int i = 0; i < h->n; ++i) {
+            int r = h->hip(hipMemcpyAsync(h->job[i].planes[0], h->ws + h->L.s[i].tune,
+                                          8 * (size_t)h->L.s[i].PW, hipMemcpyDeviceToDevice,
+                                          h->st), "restore state");
+            if (r) return r;
+        }
+        h->parity = 0;
+        h->step = step0;
+        return h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles, 0,
+                                            h->sh), "flags init");
+    };
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return h->fail(SIM_E_HIP, "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return h->fail(SIM_E_HIP, "event create");
+    }
+    const bool graphs = h->use_graphs;
+    h->use_graphs = false;
+    float best_ms = 1e30f;
+    sim_exec best_ex = ex0;
+    for (int c = 0; c < ns && !rc; ++c) {
+        const sim_exec ex{shapes[c].tr, shapes[c].tc, shapes[c].km, 1};
+        rc = sim_set_exec(h, &ex);
+        if (!rc) rc = restore();
+        if (!rc) rc = enqueue_run(h, h->st, T_probe, nullptr);   // warm-up
+        if (!rc) rc = restore();
+        if (!rc) rc = h->hip(hipEventRecord(e0, h->st), "event record");
+        if (!rc) rc = enqueue_run(h, h->st, T_probe, nullptr);
+        if (!rc) rc = h->hip(hipEventRecord(e1, h->st), "event record");
+        if (!rc) rc = h->hip(hipEventSynchronize(e1), "event sync");
+        float ms = 0.f;
+        if (!rc) rc = h->hip(hipEventElapsedTime(&ms, e0, e1), "elapsed time");
+        if (!rc && ms < best_ms) {
+            best_ms = ms;
+            best_ex = ex;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->use_graphs = graphs;
+    if (!rc) rc = sim_set_exec(h, &best_ex);
+    if (!rc) rc = restore();
+    if (!rc) h->parity = 0;
+    if (!rc && best) *best = best_ex;
+    return rc;
+}
+
+int sim_use_graphs(sim_handle* h, int32_t on) {
+    if (!h) return SIM_E_ARG;
+    h->use_graphs = on != 0;
+    if (!on) h->drop_graphs();
     return SIM_OK;
 }
 

@@ -59,6 +59,8 @@ hipError_t launch_get_state(hipStream_t st, const DevScen& job, const uint32_t* 
 hipError_t launch_flags_init(hipStream_t st, const DevScen* d_jobs, const int32_t* d_tile_job,
                              int32_t ntiles, int32_t parity, TileShape sh);
 bool step_shape_supported(TileShape sh, bool adj);
+// The compiled forward shapes (at most `max`); returns how many.
+int step_shapes(TileShape* out, int max);
 hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_jobs,
                        const int32_t* d_tile_job, int32_t ntiles, int32_t parity,
                        int32_t t_off, int32_t ksteps, int32_t skip, const float* lam,

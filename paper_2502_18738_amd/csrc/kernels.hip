@@ -53,6 +53,14 @@ __device__ __forceinline__ void philox_w01(uint32_t c0, uint32_t c1, uint32_t c2
 
 __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * kTwoM24; }
 
+// Neighbour slot e = 0..7 walks the 3 x 3 block row by row, skipping the
+// centre: (dr, dc) = (-1,-1), (-1,0), (-1,1), (0,-1), (0,1), (1,-1), (1,0), (1,1).
+__device__ __forceinline__ void slot_dir(int e, int& dr, int& dc) {
+    const int idx = e < 4 ? e : e + 1;
+    dr = idx / 3 - 1;
+    dc = idx - (idx / 3) * 3 - 1;
+}
+
 // Per-edge terms of Eq. 1-5 for a burning neighbour at offset (dr, dc) of the
 // receiving cell j.  rec = (F, V, V cos, V sin) of j.  The spread direction
 // i -> j has east component -dc and north component +dr, so the projection of
@@ -61,13 +69,13 @@ struct Edge {
     float q, ez, x, th, vterm;
 };
 
-template <int DR, int DC>
-__device__ __forceinline__ Edge edge_terms(const DevScen& J, float4 rec, float Ej, float Ei) {
-    constexpr bool diag = (DR != 0) && (DC != 0);
+__device__ __forceinline__ Edge edge_terms(const DevScen& J, float4 rec, float Ej, float Ei,
+                                           int dr, int dc) {
+    const bool diag = (dr != 0) && (dc != 0);
     Edge e;
     const float sl = (Ej - Ei) * (diag ? J.inv_l_diag : J.inv_l);
     e.th = atanf(sl) * kRad2Deg;                         // Eq. 1, degrees
-    float proj = (float)(-DC) * rec.z + (float)DR * rec.w;
+    float proj = (float)(-dc) * rec.z + (float)dr * rec.w;
     if (diag) proj = proj * kSqrtHalf;
     e.vterm = proj - rec.y;                               // V (cos(delta) - 1)
     const float z = J.c1 * rec.y + J.c2 * e.vterm + J.a * e.th;   // Eq. 3, 4 exponents
@@ -77,58 +85,42 @@ __device__ __forceinline__ Edge edge_terms(const DevScen& J, float4 rec, float E
     return e;
 }
 
-// Eq. 9 as the recurrence P <- P + q (1 - P) over the burning neighbours in
-// fixed row-major order.  `nb(dr, dc)` tells whether a neighbour burns.  When
-// ADJ, also returns d p_ignite / d(p_h, a, c1, c2) in g.
-template <bool ADJ, class NB>
-__device__ __forceinline__ float cell_pignite(const DevScen& J, int64_t j, NB nb, float g[4]) {
+// Eq. 9 for two disjoint sets of edges: 1 - (1 - a)(1 - b), written without
+// cancellation.  por(a, 0) == a and por(0, b) == b exactly, so slots without a
+// burning neighbour (q = 0) are neutral.
+__device__ __forceinline__ float por(float a, float b) { return a + b * (1.f - a); }
+
+// Eq. 9 over the 8 neighbour slots with a fixed pairing tree
+// ((0,1),(2,3)),((4,5),(6,7)).  Every kernel that evaluates p_ignite uses this
+// tree (sequentially here, across 8 lanes in combine8_lanes), so all of them
+// produce bit-identical values.
+__device__ __forceinline__ float combine8(const float q[8]) {
+    return por(por(por(q[0], q[1]), por(q[2], q[3])), por(por(q[4], q[5]), por(q[6], q[7])));
+}
+
+// The same tree across an aligned group of 8 lanes holding q of slots 0..7;
+// the result is valid in the group's first lane.
+__device__ __forceinline__ float combine8_lanes(float q) {
+    const float a = por(q, __shfl_xor(q, 1, 64));
+    const float b = por(a, __shfl_xor(a, 2, 64));
+    return por(b, __shfl_xor(b, 4, 64));
+}
+
+// p_ignite of cell j from its 8 slots, one lane; nb(dr, dc) says whether that
+// neighbour burns.
+template <class NB>
+__device__ __forceinline__ float cell_pignite(const DevScen& J, int64_t j, NB nb) {
     const float4 rec = J.rec[j];
     const float Ej = J.elev[j];
-    const int64_t W = J.W;
-    float P = 0.f;
-    float q[8], dx[8][4];
-    int k = 0;
-#define FS_EDGE(DR, DC)                                                             \
-    {                                                                               \
-        if (nb(DR, DC)) {                                                           \
-            const Edge e = edge_terms<DR, DC>(J, rec, Ej, J.elev[j + (DR) * W + (DC)]); \
-            P = P + e.q * (1.f - P);                                                \
-            if (ADJ) {                                                              \
-                q[k] = e.q;                                                         \
-                dx[k][0] = rec.x * e.ez;                                            \
-                dx[k][1] = e.x * e.th;                                              \
-                dx[k][2] = e.x * rec.y;                                             \
-                dx[k][3] = e.x * e.vterm;                                           \
-            }                                                                       \
-        } else if (ADJ) {                                                           \
-            q[k] = 0.f;                                                             \
-            dx[k][0] = dx[k][1] = dx[k][2] = dx[k][3] = 0.f;                        \
-        }                                                                           \
-        ++k;                                                                        \
+    float q[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        int dr, dc;
+        slot_dir(e, dr, dc);
+        q[e] = 0.f;
+        if (nb(dr, dc)) q[e] = edge_terms(J, rec, Ej, J.elev[j + (int64_t)dr * J.W + dc], dr, dc).q;
     }
-    FS_EDGE(-1, -1) FS_EDGE(-1, 0) FS_EDGE(-1, 1)
-    FS_EDGE(0, -1)                FS_EDGE(0, 1)
-    FS_EDGE(1, -1)  FS_EDGE(1, 0)  FS_EDGE(1, 1)
-#undef FS_EDGE
-    if (ADJ) {
-        // dP/dq_i = prod_{m != i} (1 - q_m), from prefix and suffix products so
-        // that a saturated q_m = 1 does not divide by zero.
-        float pre[8], suf[8];
-        float acc = 1.f;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) { pre[i] = acc; acc = acc * (1.f - q[i]); }
-        acc = 1.f;
-#pragma unroll
-        for (int i = 7; i >= 0; --i) { suf[i] = acc; acc = acc * (1.f - q[i]); }
-        g[0] = g[1] = g[2] = g[3] = 0.f;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const float s = pre[i] * suf[i] * (J.c * (1.f - q[i] * q[i]));
-#pragma unroll
-            for (int m = 0; m < 4; ++m) g[m] = g[m] + s * dx[i][m];
-        }
-    }
-    return P;
+    return combine8(q);
 }
 
 __device__ __forceinline__ int block_exscan(int v, int* sWave, int* total) {
@@ -173,7 +165,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
        const float* __restrict__ lam, unsigned long long* __restrict__ stats) {
     constexpr int RR = TR + 2 * KM, RC = TC + 2, NW = RR * RC;
     constexpr int WPT = (NW + 255) / 256;
-    constexpr int LCAP = 8192;
+    constexpr int LCAP = NW * 32;  // worst case: every cell of the region has a trial
     static_assert(NW * 32 < 65536, "trial list entries are 16-bit");
     static_assert(KM <= TR && KM <= 32, "halo deeper than a tile");
 
@@ -253,7 +245,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     }
     if (tid == 0) sFlag = 0;
 
-    const uint32_t k0 = J.seed_lo, k1 = J.seed_hi, scen = J.scen_id;
+    const uint32_t k0s = J.seed_lo, k1s = J.seed_hi, scen = J.scen_id;
     double gsum[4] = {0.0, 0.0, 0.0, 0.0};
     unsigned long long n_trials = 0, n_ties = 0;
     int cur = 0;
@@ -265,13 +257,14 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         const uint32_t* cB = sB[cur];
         const uint32_t* cD = sD[cur];
 
-        // trial masks of this thread's words
-        uint32_t tm[WPT];
-        int cnt = 0;
+        // trial masks of this thread's words: continue trials (burning cells)
+        // and ignition trials (burnable cells with fuel and a burning neighbour)
+        uint32_t mc[WPT], mi[WPT];
+        int cnt = 0;  // continue count | ignition count << 16
 #pragma unroll
         for (int i = 0; i < WPT; ++i) {
             const int w = tid + i * 256;
-            tm[i] = 0;
+            mc[i] = mi[i] = 0;
             if (w < NW) {
                 const int lr = w / RC, lc = w - (w / RC) * RC;
                 if (lr >= lo && lr < hi) {
@@ -281,72 +274,162 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     const uint32_t XR = lc < RC - 1 ? (cB[a + lc + 1] | cB[b + lc + 1] | cB[c + lc + 1]) : 0u;
                     const uint32_t nbm = X | (X << 1) | (X >> 1) | (XL >> 31) | (XR << 31);
                     const uint32_t bw = cB[w], dw = cD[w];
-                    tm[i] = (nbm & ~bw & ~dw & sU[w]) | bw;
-                    cnt += __popc(tm[i]);
+                    mc[i] = bw;
+                    mi[i] = nbm & ~bw & ~dw & sU[w];
+                    cnt += __popc(mc[i]) | (__popc(mi[i]) << 16);
                     sR[w] = 0;
                 }
             }
         }
-        int total;
-        const int off = block_exscan(cnt, sWave, &total);
+        int tot;
+        const int off = block_exscan(cnt, sWave, &tot);
+        const int tot_c = tot & 0xFFFF, tot_i = tot >> 16;
 
-        for (int base = 0; base < total; base += LCAP) {
-            int o = off;
+        // compacted trial list: continue entries first, then ignition entries
+        {
+            int oc = off & 0xFFFF, oi = tot_c + (off >> 16);
 #pragma unroll
             for (int i = 0; i < WPT; ++i) {
-                uint32_t m = tm[i];
                 const int w = tid + i * 256;
+                uint32_t m = mc[i];
                 while (m) {
                     const int bit = __ffs(m) - 1;
                     m &= m - 1;
-                    if (o >= base && o < base + LCAP) sL[o - base] = (uint16_t)(w * 32 + bit);
-                    ++o;
+                    sL[oc++] = (uint16_t)(w * 32 + bit);
+                }
+                m = mi[i];
+                while (m) {
+                    const int bit = __ffs(m) - 1;
+                    m &= m - 1;
+                    sL[oi++] = (uint16_t)(w * 32 + bit);
                 }
             }
-            __syncthreads();
-            const int nl = min(LCAP, total - base);
-            for (int e = tid; e < nl; e += 256) {
-                const int ent = sL[e];
-                const int w = ent >> 5, bit = ent & 31;
-                const int lr = w / RC, lc = w - (w / RC) * RC;
-                const int gr = r0 + lr;
-                const int gc = (w0 + lc) * 32 + bit;
-                const int64_t j = (int64_t)gr * J.W + gc;
-                const bool interior = lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC;
-                uint32_t rw0, rw1;
-                philox_w01((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, scen, k0,
-                           k1, rw0, rw1);
-                if ((cB[w] >> bit) & 1u) {  // burning: continue trial
-                    if (u24(rw1) < J.p_continue) atomicOr(&sR[w], 1u << bit);
-                    if (interior) ++n_trials;
-                } else {  // burnable with a burning neighbour: ignition trial
-                    const int cl = lc * 32 + bit;
-                    auto nb = [&](int dr, int dc) -> bool {
-                        const int cc = cl + dc;
-                        if (cc < 0 || cc >= RC * 32) return false;
-                        return (cB[(lr + dr) * RC + (cc >> 5)] >> (cc & 31)) & 1u;
-                    };
-                    float gl[4];
-                    const float P = cell_pignite<ADJ>(J, j, nb, gl);
-                    const float u = u24(rw0);
-                    if (u < P) {
-                        atomicOr(&sR[w], 1u << bit);
-                        if (interior) {
-                            if (J.yhat) J.yhat[j] = P;
-                            if (ADJ) {
-                                const float lj = lam[J.lam_off + j];
-                                for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj * gl[m]);
-                            }
+        }
+        __syncthreads();
+
+        // Continue trials take one lane each.  Ignition trials take an aligned
+        // group of 8 lanes (one per neighbour slot: the trial's gathers are
+        // issued together and its per-edge transcendental chains run side by
+        // side) when all trials of the step fit in one pass of the work-group;
+        // otherwise one lane each, walking its 8 slots.  Both use the same
+        // Eq. 9 pairing tree, so p_ignite is bit-identical either way.
+        const bool wide = tot_c + 8 * tot_i <= 256;
+        const int base_i = wide ? ((tot_c + 7) & ~7) : tot_c;
+        const int nslots = base_i + (wide ? 8 : 1) * tot_i;
+        for (int k0 = 0; k0 < nslots; k0 += 256) {
+            const int k = k0 + tid;
+            if (k >= nslots) continue;
+            const bool cont = k < tot_c;
+            if (!cont && k < base_i) continue;   // padding before the 8-aligned groups
+            const int e = wide ? (k & 7) : 0;
+            const int ent = cont ? sL[k] : sL[tot_c + (wide ? (k - base_i) >> 3 : k - base_i)];
+            const int w = ent >> 5, bit = ent & 31;
+            const int lr = w / RC, lc = w - (w / RC) * RC;
+            const int64_t j = (int64_t)(r0 + lr) * J.W + ((w0 + lc) * 32 + bit);
+            const bool interior = lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC;
+            uint32_t rw0, rw1;
+            philox_w01((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, scen, k0s, k1s,
+                       rw0, rw1);
+            if (cont) {
+                if (u24(rw1) < J.p_continue) atomicOr(&sR[w], 1u << bit);
+                if (interior) ++n_trials;
+                continue;
+            }
+            auto burning = [&](int dr, int dc) -> bool {
+                const int cl = lc * 32 + bit + dc;
+                return cl >= 0 && cl < RC * 32 &&
+                       ((cB[(lr + dr) * RC + (cl >> 5)] >> (cl & 31)) & 1u);
+            };
+            const float4 rec = J.rec[j];
+            const float Ej = J.elev[j];
+            float P;
+            float gl[4] = {0.f, 0.f, 0.f, 0.f};
+            if (wide) {
+                int dr, dc;
+                slot_dir(e, dr, dc);
+                const bool burn = burning(dr, dc);
+                const float Ei = burn ? J.elev[j + (int64_t)dr * J.W + dc] : 0.f;
+                Edge ed{0.f, 0.f, 0.f, 0.f, 0.f};
+                if (burn) ed = edge_terms(J, rec, Ej, Ei, dr, dc);
+                P = combine8_lanes(ed.q);
+                if (ADJ) {
+                    // d p_ignite / d q_e = prod over the other slots of (1 - q)
+                    const float om = 1.f - ed.q;
+                    const int g0 = threadIdx.x & 56;
+                    float prod = 1.f;
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        const float o = __shfl(om, g0 + m, 64);
+                        prod = prod * (m == e ? 1.f : o);
+                    }
+                    const float sc = prod * (J.c * (1.f - ed.q * ed.q));
+                    gl[0] = sc * (rec.x * ed.ez);       // dx/dp_h = F e^z
+                    gl[1] = sc * (ed.x * ed.th);        // dx/da   = x theta_s
+                    gl[2] = sc * (ed.x * rec.y);        // dx/dc1  = x V
+                    gl[3] = sc * (ed.x * ed.vterm);     // dx/dc2  = x V (cos - 1)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        gl[m] = gl[m] + __shfl_xor(gl[m], 1, 64);
+                        gl[m] = gl[m] + __shfl_xor(gl[m], 2, 64);
+                        gl[m] = gl[m] + __shfl_xor(gl[m], 4, 64);
+                    }
+                }
+            } else {
+                float q[8], dx[8][4];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    int dr, dc;
+                    slot_dir(m, dr, dc);
+                    q[m] = 0.f;
+                    dx[m][0] = dx[m][1] = dx[m][2] = dx[m][3] = 0.f;
+                    if (burning(dr, dc)) {
+                        const Edge ed =
+                            edge_terms(J, rec, Ej, J.elev[j + (int64_t)dr * J.W + dc], dr, dc);
+                        q[m] = ed.q;
+                        if (ADJ) {
+                            dx[m][0] = rec.x * ed.ez;
+                            dx[m][1] = ed.x * ed.th;
+                            dx[m][2] = ed.x * rec.y;
+                            dx[m][3] = ed.x * ed.vterm;
                         }
                     }
-                    if (interior) {
-                        ++n_trials;
-                        if (fabsf(u - P) <= kTieEps) ++n_ties;
+                }
+                P = combine8(q);
+                if (ADJ) {
+                    float pre[8], suf[8], acc = 1.f;
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) { pre[m] = acc; acc = acc * (1.f - q[m]); }
+                    acc = 1.f;
+#pragma unroll
+                    for (int m = 7; m >= 0; --m) { suf[m] = acc; acc = acc * (1.f - q[m]); }
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        const float sc = pre[m] * suf[m] * (J.c * (1.f - q[m] * q[m]));
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) gl[d] = gl[d] + sc * dx[m][d];
                     }
                 }
             }
-            __syncthreads();
+            if (e == 0) {
+                const float u = u24(rw0);
+                if (u < P) {
+                    atomicOr(&sR[w], 1u << bit);
+                    if (interior) {
+                        if (J.yhat) J.yhat[j] = P;
+                        if (ADJ) {
+                            const float lj = lam[J.lam_off + j];
+#pragma unroll
+                            for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj * gl[m]);
+                        }
+                    }
+                }
+                if (interior) {
+                    ++n_trials;
+                    if (fabsf(u - P) <= kTieEps) ++n_ties;
+                }
+            }
         }
+        __syncthreads();
 
         // combine: burning' = successful trials; burned' = burned | burnt out
 #pragma unroll
@@ -540,20 +623,24 @@ k_get_state(int32_t H, int32_t W, int32_t pitch, const uint32_t* __restrict__ pl
     out[(int64_t)H * W + j] = (uint8_t)((planes[PW + o] >> (c & 31)) & 1u);
 }
 
+// One wavefront per tile: OR of the burning bit-plane over the tile.
 __global__ void __launch_bounds__(256)
 k_flags_init(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job,
              int32_t ntiles, int32_t parity, int32_t TR, int32_t TC) {
-    const int g = blockIdx.x * 256 + threadIdx.x;
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (g >= ntiles) return;
     const DevScen& J = jobs[tile_job[g]];
     const int lt = g - J.tile0;
     const int trow = lt / J.tiles_c, tcol = lt - trow * J.tiles_c;
     const uint32_t* p = J.planes[parity];
-    uint32_t any = 0;
-    for (int r = trow * TR; r < min(J.H, trow * TR + TR); ++r)
-        for (int w = tcol * TC; w < min(J.pitch, tcol * TC + TC); ++w)
-            any |= p[(int64_t)r * J.pitch + w];
-    J.flags[parity][lt] = any ? 1 : 0;   // other buffer not known to match
+    bool any = false;
+    for (int w = lane; w < TR * TC; w += 64) {
+        const int r = trow * TR + w / TC, c = tcol * TC + w % TC;
+        if (r < J.H && c < J.pitch) any |= p[(int64_t)r * J.pitch + c] != 0u;
+    }
+    any = __ballot(any) != 0ull;
+    if (lane == 0) J.flags[parity][lt] = any ? 1 : 0;   // other buffer not known to match
 }
 
 __global__ void __launch_bounds__(256)
@@ -574,8 +661,7 @@ k_pignite(const DevScen* __restrict__ job, int32_t parity, float* __restrict__ o
     const bool fuel = (J.fuel[(int64_t)r * pitch + (c >> 5)] >> (c & 31)) & 1u;
     if (fuel && !bit(B, r, c) && !bit(D, r, c)) {
         auto nb = [&](int dr, int dc) -> bool { return bit(B, r + dr, c + dc); };
-        float g[4];
-        P = cell_pignite<false>(J, j, nb, g);
+        P = cell_pignite(J, j, nb);
     }
     out[j] = P;
 }
@@ -833,7 +919,7 @@ hipError_t launch_get_state(hipStream_t st, const DevScen& J, const uint32_t* pl
 hipError_t launch_flags_init(hipStream_t st, const DevScen* d_jobs, const int32_t* d_tile_job,
                              int32_t ntiles, int32_t parity, TileShape sh) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flags_init, dim3((ntiles + 255) / 256), dim3(256), 0, st, d_jobs,
+    hipLaunchKernelGGL(k_flags_init, dim3((ntiles + 3) / 4), dim3(256), 0, st, d_jobs,
                        d_tile_job, ntiles, parity, sh.tr, sh.tc);
     return hipGetLastError();
 }
@@ -892,6 +978,9 @@ const StepEntry kSteps[] = {
     FS_SHAPE(32, 4, 1) FS_SHAPE(32, 4, 8) FS_SHAPE(32, 4, 16)
     FS_SHAPE(32, 8, 1) FS_SHAPE(32, 8, 8) FS_SHAPE(32, 8, 16)
     FS_SHAPE(8, 16, 1) FS_SHAPE(8, 16, 4) FS_SHAPE(8, 16, 8)
+    FS_SHAPE(8, 4, 1) FS_SHAPE(8, 4, 4) FS_SHAPE(8, 4, 8)
+    FS_SHAPE(8, 8, 1) FS_SHAPE(8, 8, 4) FS_SHAPE(8, 8, 8)
+    FS_SHAPE(16, 2, 1) FS_SHAPE(16, 2, 4) FS_SHAPE(16, 2, 8) FS_SHAPE(16, 2, 16)
 };
 #undef FS_SHAPE
 
@@ -903,6 +992,13 @@ const StepEntry* find_step(TileShape sh, bool adj) {
 }  // namespace
 
 bool step_shape_supported(TileShape sh, bool adj) { return find_step(sh, adj) != nullptr; }
+
+int step_shapes(TileShape* out, int max) {
+    int n = 0;
+    for (const auto& e : kSteps)
+        if (!e.adj && n < max) out[n++] = TileShape{e.tr, e.tc, e.km};
+    return n;
+}
 
 hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_jobs,
                        const int32_t* d_tile_job, int32_t ntiles, int32_t parity,

@@ -48,6 +48,7 @@ class Sim:
         self.shapes = [(int(s.H), int(s.W)) for s in scenarios]
         self.offsets = np.concatenate([[0], np.cumsum([h * w for h, w in self.shapes])])
         self.calib = bool(calib)
+        self.p_continue = [float(np.float32(s.p_continue)) for s in scenarios]
         flags = (_abi.SIM_F_CALIB if calib else 0) | (_abi.SIM_F_STATS if stats else 0)
         if calib and T_max is None:
             T_max = max(int(getattr(s, "T", 0)) for s in scenarios)
@@ -114,6 +115,17 @@ class Sim:
         return dict(tile_rows=e.tile_rows, tile_words=e.tile_words, depth=e.depth,
                     skip=bool(e.skip))
 
+    def autotune(self, T_probe: int = 32) -> dict:
+        """Time every compiled execution shape over T_probe steps from the
+        current state (restored afterwards) and keep the fastest."""
+        e = _abi.sim_exec()
+        self._check(self._lib.sim_autotune(self._h, int(T_probe), ctypes.byref(e)))
+        return dict(tile_rows=e.tile_rows, tile_words=e.tile_words, depth=e.depth,
+                    skip=bool(e.skip))
+
+    def use_graphs(self, on: bool = True):
+        self._check(self._lib.sim_use_graphs(self._h, int(bool(on))))
+
     def run(self, T: int):
         self._check(self._lib.sim_run(self._h, int(T)))
 
@@ -131,6 +143,7 @@ class Sim:
         rows = [tuple(float(x) for x in r) for r in params]
         arr = (_abi.sim_params * self.n)(*[_abi.sim_params(*r) for r in rows])
         self._check(self._lib.sim_set_params(self._h, arr))
+        self.p_continue = [float(np.float32(r[4])) for r in rows]
 
     def reset(self, seeds: Optional[Sequence[int]] = None):
         if seeds is None:
