@@ -67,6 +67,40 @@ def load_traffic(name):
     return d
 
 
+def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes,
+                       kernel_regex, out_json):
+    """Per-launch HBM bytes of the kernels matching `kernel_regex` from two
+    rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each
+    scaled by what the same counter reads for a plain device copy of
+    `copy_bytes` bytes."""
+    import csv
+    import re
+
+    def per_dispatch(path, counter, regex):
+        vals = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter and re.search(regex, r["Kernel_Name"]):
+                vals[r["Dispatch_Id"]] = vals.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
+        return list(vals.values())
+
+    def largest(path, counter):
+        return max(per_dispatch(path, counter, "copyBuffer|elementwise|copy"))
+
+    f_fetch = copy_bytes / (largest(copy_fetch_csv, "FETCH_SIZE") * 1024.0)
+    f_write = copy_bytes / (largest(copy_write_csv, "WRITE_SIZE") * 1024.0)
+    fk = per_dispatch(fetch_csv, "FETCH_SIZE", kernel_regex)
+    wk = per_dispatch(write_csv, "WRITE_SIZE", kernel_regex)
+    fetch_b = sum(fk) / len(fk) * 1024.0 * f_fetch
+    write_b = sum(wk) / len(wk) * 1024.0 * f_write
+    out = {"kernel_regex": kernel_regex, "kernel_source_sha": kernel_source_hash(),
+           "dispatches": [len(fk), len(wk)],
+           "fetch_KiB_per_dispatch": sum(fk) / len(fk), "write_KiB_per_dispatch": sum(wk) / len(wk),
+           "copy_scale": {"fetch": f_fetch, "write": f_write, "copy_bytes": copy_bytes},
+           "bytes_per_launch": fetch_b + write_b, "fetch_bytes": fetch_b, "write_bytes": write_b}
+    json.dump(out, open(out_json, "w"), indent=1)
+    print(json.dumps(out))
+
+
 def timed(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -213,8 +247,14 @@ def leg_batched(args, torch, Sim, synth):
     n, T = 256, 300
     log("batched: generating", n, "scenarios")
     scs = [synth.config3_scenario(b, T=T) for b in range(n)]
-    ex = dict(tile_rows=16, tile_words=8, depth=8, skip=True)
-    sim = Sim(scs, exec=ex)
+    sim = Sim(scs)
+    if args.autotune:
+        sim.run(150)
+        ex = sim.autotune(16)
+        sim.reset()
+    else:
+        ex = dict(DEFAULT_EXEC)
+        sim.set_exec(**ex)
 
     def run():
         sim.reset()
@@ -256,7 +296,15 @@ def main():
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--summarize-counters", nargs=7, default=None,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
+                             "COPY_BYTES", "KERNEL_REGEX", "OUT_JSON"),
+                    help="write per-launch HBM traffic from rocprofv3 counter CSVs")
     args = ap.parse_args()
+    if args.summarize_counters:
+        a = args.summarize_counters
+        summarize_counters(a[0], a[1], a[2], a[3], int(a[4]), a[5], a[6])
+        return
     if args.copy_ref:
         import torch
         a = torch.empty(args.copy_ref // 4, dtype=torch.float32, device="cuda")

@@ -191,6 +191,23 @@ SIM_API int sim_accumulator(sim_handle* h, int32_t s, float* out);
  * concatenated; grad: device FP64, n x 4.  Calibration mode only. */
 SIM_API int sim_adjoint(sim_handle* h, const float* dL_dyhat, double* grad);
 
+/* Adjoint used by sim_adjoint and sim_loss_grad.
+ *   SIM_ADJ_CHECKPOINT (default): recompute every checkpoint segment of the
+ *     last run (all segments of all scenarios in one launch sequence).
+ *   SIM_ADJ_TIMEMAP: one pass over the cells; the forward records each
+ *     cell's ignition and burn-out steps, from which the burning neighbours
+ *     at t_j - 1 of every ignited cell j are rebuilt exactly.
+ * Both return the same gradient (up to the order of the FP64 sums).
+ * Step rings (Sec. 2.3, "update by step rings"): only cells ignited at an
+ * attached step contribute -- steps 1..r_first, the last r_last steps, and
+ * r_between steps spread evenly in between (step r_first + round(k * span /
+ * (r_between + 1)), k = 1..r_between, span = T - r_first - r_last).
+ * r_first < 0 attaches every step (the default). */
+#define SIM_ADJ_CHECKPOINT 0
+#define SIM_ADJ_TIMEMAP 1
+SIM_API int sim_set_adjoint(sim_handle* h, int32_t method, int32_t r_first, int32_t r_between,
+                            int32_t r_last);
+
 /* Eq. 10 loss of the accumulator against `target` (device uint8, the n grids
  * concatenated, non-zero = observed fire) and its gradient: loss is device
  * FP64 n, grad device FP64 n x 4 (p_h, a, c1, c2).  Calibration mode only. */

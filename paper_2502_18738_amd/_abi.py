@@ -27,6 +27,9 @@ SIM_LOSS_BCE = 0
 SIM_LOSS_BCE_MSE = 1
 SIM_LOSS_MSE = 2
 
+SIM_ADJ_CHECKPOINT = 0
+SIM_ADJ_TIMEMAP = 1
+
 ERROR_NAMES = {
     SIM_E_ARG: "SIM_E_ARG", SIM_E_SHAPE: "SIM_E_SHAPE", SIM_E_PARAM: "SIM_E_PARAM",
     SIM_E_WORKSPACE: "SIM_E_WORKSPACE", SIM_E_HIP: "SIM_E_HIP", SIM_E_STATE: "SIM_E_STATE",
@@ -61,6 +64,7 @@ EXPORTS = (
     "sim_get_step", "sim_set_params", "sim_reset", "sim_get_state", "sim_set_state",
     "sim_pignite", "sim_accumulator", "sim_adjoint", "sim_loss_grad", "sim_stats",
     "sim_last_error", "sim_destroy", "sim_version", "sim_autotune", "sim_use_graphs",
+    "sim_set_adjoint",
 )
 
 _lib = None
@@ -104,6 +108,7 @@ def load():
         "sim_version": (ctypes.c_char_p, []),
         "sim_autotune": (ctypes.c_int, [H, i32, ctypes.POINTER(sim_exec)]),
         "sim_use_graphs": (ctypes.c_int, [H, i32]),
+        "sim_set_adjoint": (ctypes.c_int, [H, i32, i32, i32, i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

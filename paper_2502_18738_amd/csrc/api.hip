@@ -32,12 +32,14 @@ struct ScenLayout {
     int32_t pitch;
     int64_t PW;          // words per bit-plane
     int64_t max_tiles;   // flag capacity
-    size_t rec, fuel, planes[2], flags[2], yhat, ckpt, tune;
+    size_t rec, th8, q8, fuel, planes[2], flags[2], yhat, ckpt, tune, tign, tout;
 };
 
 struct Layout {
     size_t err, stats, box, part, jobs, tile_job, adj_jobs, adj_tile_job, gpart, ranges, lam,
-        total;
+        cell0, bl0, gpart_tmap, total;
+    int64_t total_cells;
+    int32_t tmap_blocks;
     std::vector<ScenLayout> s;
     std::vector<size_t> adj_planes[2], adj_flags[2];  // per (s, seg)
     int nseg;
@@ -61,6 +63,9 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
     for (int i = 0; i < n; ++i) max_h = std::max<int64_t>(max_h, d[i].H);
     L->part = take(2 * sizeof(double) * (size_t)cdiv(max_h, 4));
     L->jobs = take(sizeof(fs::DevScen) * (size_t)n);
+    L->cell0 = take(sizeof(int64_t) * (size_t)(n + 1));
+    L->total_cells = 0;
+    for (int i = 0; i < n; ++i) L->total_cells += (int64_t)d[i].H * d[i].W;
     int64_t tiles = 0;
     for (int i = 0; i < n; ++i) {
         ScenLayout& s = L->s[i];
@@ -75,19 +80,24 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         ScenLayout& s = L->s[i];
         const int64_t cells = (int64_t)d[i].H * d[i].W;
         s.rec = take(16 * (size_t)cells);
+        s.th8 = take(32 * (size_t)cells);
+        s.q8 = take(32 * (size_t)cells);
         s.fuel = take(4 * (size_t)s.PW);
         s.planes[0] = take(8 * (size_t)s.PW);
         s.planes[1] = take(8 * (size_t)s.PW);
         s.flags[0] = take((size_t)s.max_tiles);
         s.flags[1] = take((size_t)s.max_tiles);
-        s.yhat = s.ckpt = s.tune = 0;
+        s.yhat = s.ckpt = s.tune = s.tign = s.tout = 0;
         if (!calib) s.tune = take(8 * (size_t)s.PW);   // state saved while autotuning
         if (calib) {
             s.yhat = take(4 * (size_t)cells);
+            s.tign = take(4 * (size_t)cells);
+            s.tout = take(4 * (size_t)cells);
             s.ckpt = take(8 * (size_t)s.PW * (size_t)L->nseg);
         }
     }
-    L->adj_jobs = L->adj_tile_job = L->gpart = L->ranges = L->lam = 0;
+    L->adj_jobs = L->adj_tile_job = L->gpart = L->ranges = L->lam = L->bl0 = L->gpart_tmap = 0;
+    L->tmap_blocks = 0;
     L->adj_max_tiles_total = 0;
     for (int k = 0; k < 2; ++k) {
         L->adj_planes[k].clear();
@@ -102,6 +112,11 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         int64_t cells = 0;
         for (int i = 0; i < n; ++i) cells += (int64_t)d[i].H * d[i].W;
         L->lam = take(4 * (size_t)cells);   // dL/dyhat of all scenarios, concatenated
+        int64_t blocks = 0;
+        for (int i = 0; i < n; ++i) blocks += cdiv((int64_t)d[i].H * d[i].W, 256);
+        L->tmap_blocks = (int32_t)blocks;
+        L->bl0 = take(sizeof(int32_t) * (size_t)(n + 1));
+        L->gpart_tmap = take(4 * sizeof(double) * (size_t)blocks);
         for (int i = 0; i < n; ++i)
             for (int g = 0; g < L->nseg; ++g)
                 for (int k = 0; k < 2; ++k) {
@@ -196,6 +211,11 @@ struct sim_handle {
     };
     std::vector<Graph> graphs;
     bool use_graphs = true;
+    bool q_dirty = true;            // q8 tables must be rebuilt before the next step
+    int adj_method = 0;             // 0: checkpoint recompute, 1: time maps
+    fs::Rings rings{-1, 0, 0, 0};   // step-ring attach set (first < 0: every step)
+    std::vector<int32_t> bl0;
+    std::vector<int64_t> cell0;
     hipStream_t cap = nullptr;      // private stream used only for capture
 
     void drop_graphs() {
@@ -274,10 +294,11 @@ int save_ckpt(sim_handle* h, int slot) {
 int reset_state(sim_handle* h) {
     h->parity = 0;
     h->step = 0;
+    h->q_dirty = true;   // every run from a reset rebuilds the propagation table
     for (int i = 0; i < h->n; ++i) {
         const fs::DevScen& J = h->job[i];
         int rc = h->hip(fs::launch_init_state(h->st, J, h->d[i].f.init_burning, J.planes[0],
-                                              J.yhat), "init state");
+                                              J.yhat, J.tign, J.tout), "init state");
         if (rc) return rc;
     }
     int rc = h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles, 0,
@@ -376,15 +397,19 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
         J.c = kC;
         J.elev = d.f.elevation_m;
         J.rec = reinterpret_cast<const float4*>(h->ws + s.rec);
+        J.th8 = reinterpret_cast<const float*>(h->ws + s.th8);
+        J.q8 = reinterpret_cast<float*>(h->ws + s.q8);
         J.fuel = reinterpret_cast<const uint32_t*>(h->ws + s.fuel);
         J.planes[0] = reinterpret_cast<uint32_t*>(h->ws + s.planes[0]);
         J.planes[1] = reinterpret_cast<uint32_t*>(h->ws + s.planes[1]);
         J.flags[0] = reinterpret_cast<uint8_t*>(h->ws + s.flags[0]);
         J.flags[1] = reinterpret_cast<uint8_t*>(h->ws + s.flags[1]);
         J.yhat = h->calib() ? reinterpret_cast<float*>(h->ws + s.yhat) : nullptr;
+        J.tign = h->calib() ? reinterpret_cast<int32_t*>(h->ws + s.tign) : nullptr;
+        J.tout = h->calib() ? reinterpret_cast<int32_t*>(h->ws + s.tout) : nullptr;
         J.ckpt = h->calib() ? reinterpret_cast<uint32_t*>(h->ws + s.ckpt) : nullptr;
         J.gpart = nullptr;
-        J.lam_off = 0;
+        J.lam_off = 0;   // set below: offset of this scenario's grid in dL/dyhat
         h->max_words = std::max<int64_t>(h->max_words, s.PW);
     }
 
@@ -399,7 +424,23 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
                                         const_cast<uint32_t*>(J.fuel), J.yhat, h->d_err()),
                     "prologue");
     }
-    if (!rc) rc = rebuild_tiles(h);
+    for (int i = 0; i < n && !rc; ++i)
+        rc = h->hip(fs::launch_slopes(h->st, h->job[i], const_cast<float*>(h->job[i].th8)),
+                    "slope table");
+    h->cell0.assign(1, 0);
+    for (int i = 0; i < n; ++i) h->cell0.push_back(h->cell0.back() + (int64_t)descs[i].H * descs[i].W);
+    for (int i = 0; i < n; ++i) h->job[i].lam_off = h->cell0[i];
+    if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.cell0, h->cell0.data(),
+                                        sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, h->st),
+                         "upload cell offsets");
+    if (!rc && h->calib()) {
+        h->bl0.assign(1, 0);
+        for (int i = 0; i < n; ++i)
+            h->bl0.push_back(h->bl0.back() + (int32_t)cdiv((int64_t)descs[i].H * descs[i].W, 256));
+        rc = h->hip(hipMemcpyAsync(h->ws + h->L.bl0, h->bl0.data(), sizeof(int32_t) * (n + 1),
+                                   hipMemcpyHostToDevice, h->st), "upload block offsets");
+    }
+    if (!rc) rc = rebuild_tiles(h);   // synchronises the stream
     if (!rc) rc = reset_state(h);
     int bad = 0;
     if (!rc) rc = h->hip(hipMemcpyAsync(&bad, h->d_err(), sizeof(int), hipMemcpyDeviceToHost,
@@ -458,7 +499,8 @@ int enqueue_run(sim_handle* h, hipStream_t st, int T, unsigned long long* stats)
         int k = std::min(h->ex.depth, T);
         if (h->calib()) k = std::min(k, h->ckpt_every - h->step % h->ckpt_every);
         int rc = h->hip(fs::launch_step(st, h->sh, false, h->d_jobs(), h->d_tile_job(), h->ntiles,
-                                        h->parity, h->step, k, h->ex.skip, nullptr, stats),
+                                        h->parity, h->step, k, h->ex.skip, nullptr,
+                                        fs::Rings{-1, 0, 0, 0}, stats),
                         "step kernel");
         if (rc) return rc;
         ++h->launches;
@@ -473,6 +515,17 @@ int enqueue_run(sim_handle* h, hipStream_t st, int T, unsigned long long* stats)
         }
     }
     return SIM_OK;
+}
+
+// Rebuild the per-edge propagation table (Eq. 2-5 for every edge) if the
+// parameters changed or a new run started since it was built.
+int ensure_qtable(sim_handle* h) {
+    if (!h->q_dirty) return SIM_OK;
+    int rc = h->hip(fs::launch_qtable(h->st, h->d_jobs(),
+                                      reinterpret_cast<const int64_t*>(h->ws + h->L.cell0), h->n,
+                                      h->L.total_cells), "propagation table");
+    if (!rc) h->q_dirty = false;
+    return rc;
 }
 
 bool same_exec(const sim_exec& a, const sim_exec& b) {
@@ -547,6 +600,8 @@ int sim_run(sim_handle* h, int32_t T) {
         return h->fail(SIM_E_STATE, "calibration run would pass T_max = %d", h->T_max);
     if ((int64_t)h->step + T > INT_MAX / 2) return h->fail(SIM_E_SHAPE, "step counter overflow");
     if (T == 0) return SIM_OK;
+    int qrc = ensure_qtable(h);
+    if (qrc) return qrc;
     unsigned long long* stats = (h->flags & SIM_F_STATS) ? h->d_stats() : nullptr;
     if (h->use_graphs && !stats && T > h->ex.depth) {
         const int rc = run_graph(h, T);
@@ -561,6 +616,7 @@ int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best) {
     if (T_probe < 1 || T_probe > 4096) return h->fail(SIM_E_SHAPE, "T_probe must be in [1, 4096]");
     fs::TileShape shapes[64];
     const int ns = fs::step_shapes(shapes, 64);
+    if (int r = ensure_qtable(h)) return r;
     const int step0 = h->step, par0 = h->parity;
     const sim_exec ex0 = h->ex;
     int rc = SIM_OK;
@@ -663,6 +719,7 @@ int sim_set_params(sim_handle* h, const sim_params* p) {
         if (rc) return rc;
     }
     h->adj_T = -1;  // adjoint jobs copy the parameters
+    h->q_dirty = true;
     return SIM_OK;
 }
 
@@ -758,6 +815,7 @@ int build_adjoint(sim_handle* h, int T) {
             J.t_base = sg * h->ckpt_every;
             J.t_end = std::min((sg + 1) * h->ckpt_every, T);
             J.yhat = nullptr;
+            J.tign = J.tout = nullptr;
             J.gpart = reinterpret_cast<double*>(h->ws + h->L.gpart);
             J.tile0 = g;
             const int32_t nt = J.tiles_r * J.tiles_c;
@@ -792,6 +850,19 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
     if (T == 0)
         return h->hip(hipMemsetAsync(grad, 0, sizeof(double) * 4 * (size_t)h->n, h->st),
                       "zero gradient");
+    fs::Rings rg = h->rings;
+    rg.T = T;
+    if (h->adj_method == 1) {
+        auto* gp = reinterpret_cast<double*>(h->ws + h->L.gpart_tmap);
+        int rc = h->hip(fs::launch_adjoint_tmap(h->st, h->d_jobs(),
+                                                reinterpret_cast<const int32_t*>(h->ws + h->L.bl0),
+                                                h->n, h->L.tmap_blocks, lam, rg, gp),
+                        "time-map adjoint");
+        if (!rc) rc = h->hip(fs::launch_grad_reduce(h->st, gp,
+                                                    reinterpret_cast<int32_t*>(h->ws + h->L.bl0),
+                                                    h->n, grad), "reduce gradient");
+        return rc;
+    }
     int rc = SIM_OK;
     if (h->adj_T != T) rc = build_adjoint(h, T);
     if (rc) return rc;
@@ -808,7 +879,7 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
     for (int off = 0; off < h->ckpt_every && !rc; ) {
         const int k = std::min(h->ex.depth, h->ckpt_every - off);
         rc = h->hip(fs::launch_step(h->st, h->sh, true, d_adj, d_adj_tiles, h->adj_ntiles,
-                                    parity, off, k, h->ex.skip, lam, stats), "adjoint kernel");
+                                    parity, off, k, h->ex.skip, lam, rg, stats), "adjoint kernel");
         parity ^= 1;
         off += k;
     }
@@ -819,6 +890,19 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
 }
 
 }  // namespace
+
+int sim_set_adjoint(sim_handle* h, int32_t method, int32_t r_first, int32_t r_between,
+                    int32_t r_last) {
+    if (!h) return SIM_E_ARG;
+    if (method != SIM_ADJ_CHECKPOINT && method != SIM_ADJ_TIMEMAP)
+        return h->fail(SIM_E_ARG, "unknown adjoint method %d", method);
+    if (r_first >= 0 && (r_between < 0 || r_last < 0))
+        return h->fail(SIM_E_ARG, "step-ring counts must be >= 0");
+    h->adj_method = method;
+    h->rings = fs::Rings{r_first < 0 ? -1 : r_first, r_first < 0 ? 0 : r_between,
+                         r_first < 0 ? 0 : r_last, 0};
+    return SIM_OK;
+}
 
 int sim_adjoint(sim_handle* h, const float* dL_dyhat, double* grad) {
     if (!h) return SIM_E_ARG;

@@ -4,6 +4,12 @@
 //   rec     float4 per cell: (F, V, V cos(theta_w), V sin(theta_w)) with
 //           F = (1 + p_veg)(1 + p_den), the fuel factors of Eq. 2 multiplied
 //           once, and the wind heading resolved into east/north components.
+//   th8     8 floats per cell: the Eq. 1 slope angle (degrees) from each
+//           neighbour slot toward the cell (static, built once).
+//   q8      8 floats per cell: f_p(p_propagate) of the edge from each
+//           neighbour slot into the cell for the current parameters (Eq. 2-5),
+//           rebuilt at the start of a run whenever parameters or the run
+//           changed.  Slot order: (dr, dc) row by row, centre skipped.
 //   fuel    one bit per cell (F > 0), rows of `pitch` 32-bit words.
 //   planes  two ping-pong buffers; each holds the burning bit-plane followed
 //           by the burned bit-plane (2 * H * pitch words): 2 bits per cell.
@@ -31,13 +37,24 @@ struct DevScen {
     int32_t pad0;
     const float* elev;         // caller's elevation field
     const float4* rec;         // per-cell record
+    const float* th8;          // slope (Eq. 1, degrees) toward each of the 8 neighbours
+    float* q8;                 // f_p(p_propagate) of each of the 8 incoming edges (per run)
     const uint32_t* fuel;      // fuel bit-plane
     uint32_t* planes[2];       // ping-pong state buffers
     uint8_t* flags[2];         // per-tile flags, per parity
     float* yhat;               // accumulator or nullptr
+    int32_t* tign;             // step each cell ignited (0: initially burning) or nullptr
+    int32_t* tout;             // step each cell burnt out, or nullptr
     uint32_t* ckpt;            // checkpoint store (forward) / own segment (adjoint)
     double* gpart;             // per-tile gradient partials (adjoint jobs)
     int64_t lam_off;           // offset of this scenario's dL/dyhat grid
+};
+
+// Step-ring attach set of the adjoint (Sec. 2.3): ignition steps t with
+// t <= first, or t > T - last, or t one of `between` steps spread evenly in
+// between; first < 0 attaches every step.
+struct Rings {
+    int32_t first, between, last, T;
 };
 
 struct TileShape {
@@ -50,8 +67,19 @@ hipError_t launch_prologue(hipStream_t st, const DevScen* d_job, const DevScen& 
                            const float* p_veg, const float* p_den, const float* ws,
                            const float* wd, float ws0, float wd0, const uint8_t* ign,
                            float4* rec, uint32_t* fuel, float* yhat, int* d_err);
+// Slope table th8 of one scenario from its elevation (after the prologue).
+hipError_t launch_slopes(hipStream_t st, const DevScen& job, float* th8);
+// Propagation table q8 of every scenario for the current parameters.
+// d_cell0: n + 1 prefix sums of cell counts (block ranges per scenario).
+hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
+                         int64_t total_cells);
 hipError_t launch_init_state(hipStream_t st, const DevScen& job, const uint8_t* ign,
-                             uint32_t* planes, float* yhat);
+                             uint32_t* planes, float* yhat, int32_t* tign, int32_t* tout);
+// Time-map adjoint: one pass over every cell of every scenario; bl0 = n + 1
+// prefix sums of ceil(cells / 256) per scenario; writes gpart[block][4].
+hipError_t launch_adjoint_tmap(hipStream_t st, const DevScen* d_jobs, const int32_t* d_bl0,
+                               int32_t n, int32_t nblocks, const float* lam, Rings rings,
+                               double* gpart);
 hipError_t launch_set_state(hipStream_t st, const DevScen& job, const uint8_t* in,
                             uint32_t* planes, int* d_err);
 hipError_t launch_get_state(hipStream_t st, const DevScen& job, const uint32_t* planes,
@@ -64,7 +92,7 @@ int step_shapes(TileShape* out, int max);
 hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_jobs,
                        const int32_t* d_tile_job, int32_t ntiles, int32_t parity,
                        int32_t t_off, int32_t ksteps, int32_t skip, const float* lam,
-                       unsigned long long* d_stats);
+                       Rings rings, unsigned long long* d_stats);
 // Copy each job's current planes into checkpoint slot `slot` (forward jobs).
 hipError_t launch_ckpt_save(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
                             int32_t slot, int64_t max_words);

@@ -9,7 +9,7 @@
 // Only those trial cells touch the per-cell fields: the fire front is a thin
 // ring, so per-edge transcendental work (Eq. 1-5) and field gathers scale with
 // the front, not with the grid.  Trials are compacted into an LDS list by a
-// work-group prefix sum and dealt round-robin to the 256 lanes, so one busy
+// work-group prefix sum and dealt round-robin to the work-group's lanes, so one busy
 // word does not serialise a wavefront.
 //
 // Compiled with -ffp-contract=off: every FP32 operation rounds as written, so
@@ -20,6 +20,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <climits>
 
 namespace fs {
 
@@ -61,20 +62,26 @@ __device__ __forceinline__ void slot_dir(int e, int& dr, int& dc) {
     dc = idx - (idx / 3) * 3 - 1;
 }
 
-// Per-edge terms of Eq. 1-5 for a burning neighbour at offset (dr, dc) of the
-// receiving cell j.  rec = (F, V, V cos, V sin) of j.  The spread direction
-// i -> j has east component -dc and north component +dr, so the projection of
-// the wind on it is (-dc * Vc + dr * Vs) / |(dr, dc)|.
+// Eq. 1: slope angle in degrees from neighbour i = (r + dr, c + dc) up to
+// the receiving cell j (uphill spread is positive).
+__device__ __forceinline__ float slope_deg(const DevScen& J, float Ej, float Ei, int dr, int dc) {
+    const bool diag = (dr != 0) && (dc != 0);
+    return atanf((Ej - Ei) * (diag ? J.inv_l_diag : J.inv_l)) * kRad2Deg;
+}
+
+// Per-edge terms of Eq. 2-5 for the edge from neighbour slot (dr, dc) into the
+// receiving cell j.  rec = (F, V, V cos, V sin) of j, th = the Eq. 1 slope.
+// The spread direction i -> j has east component -dc and north component
+// +dr, so the projection of the wind on it is (-dc * Vc + dr * Vs) / |(dr, dc)|.
 struct Edge {
     float q, ez, x, th, vterm;
 };
 
-__device__ __forceinline__ Edge edge_terms(const DevScen& J, float4 rec, float Ej, float Ei,
-                                           int dr, int dc) {
+__device__ __forceinline__ Edge edge_terms(const DevScen& J, float4 rec, float th, int dr,
+                                           int dc) {
     const bool diag = (dr != 0) && (dc != 0);
     Edge e;
-    const float sl = (Ej - Ei) * (diag ? J.inv_l_diag : J.inv_l);
-    e.th = atanf(sl) * kRad2Deg;                         // Eq. 1, degrees
+    e.th = th;
     float proj = (float)(-dc) * rec.z + (float)dr * rec.w;
     if (diag) proj = proj * kSqrtHalf;
     e.vterm = proj - rec.y;                               // V (cos(delta) - 1)
@@ -111,18 +118,70 @@ __device__ __forceinline__ float combine8_lanes(float q) {
 template <class NB>
 __device__ __forceinline__ float cell_pignite(const DevScen& J, int64_t j, NB nb) {
     const float4 rec = J.rec[j];
-    const float Ej = J.elev[j];
     float q[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         int dr, dc;
         slot_dir(e, dr, dc);
         q[e] = 0.f;
-        if (nb(dr, dc)) q[e] = edge_terms(J, rec, Ej, J.elev[j + (int64_t)dr * J.W + dc], dr, dc).q;
+        if (nb(dr, dc)) q[e] = edge_terms(J, rec, J.th8[j * 8 + e], dr, dc).q;
     }
     return combine8(q);
 }
 
+// Step-ring attach test (Sec. 2.3, "update by step rings").
+__device__ __forceinline__ bool attached(const Rings& rg, int t) {
+    if (rg.first < 0) return true;
+    if (t <= rg.first || t > rg.T - rg.last) return true;
+    const int span = rg.T - rg.first - rg.last;
+    for (int k = 1; k <= rg.between; ++k)
+        if (t == rg.first + (int)(((long long)k * span + (rg.between + 1) / 2) / (rg.between + 1)))
+            return true;
+    return false;
+}
+
+// p_ignite (Eq. 9, the fixed tree) of cell j and its derivatives with respect
+// to (p_h, a, c1, c2) for the burning-neighbour slots nb(dr, dc), one lane:
+// dP/dq_m = prod over the other slots of (1 - q) (prefix x suffix products, so
+// a saturated q = 1 never divides), dq/dx = c (1 - q^2) and
+// dx/d(p_h, a, c1, c2) = (F e^z, x theta_s, x V, x V (cos - 1)).
+template <class NB>
+__device__ __forceinline__ float pignite_grad(const DevScen& J, int64_t j, NB nb, float gl[4]) {
+    const float4 rec = J.rec[j];
+    float q[8], dx[8][4];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        int dr, dc;
+        slot_dir(m, dr, dc);
+        q[m] = 0.f;
+        dx[m][0] = dx[m][1] = dx[m][2] = dx[m][3] = 0.f;
+        if (nb(dr, dc)) {
+            const Edge ed = edge_terms(J, rec, J.th8[j * 8 + m], dr, dc);
+            q[m] = ed.q;
+            dx[m][0] = rec.x * ed.ez;
+            dx[m][1] = ed.x * ed.th;
+            dx[m][2] = ed.x * rec.y;
+            dx[m][3] = ed.x * ed.vterm;
+        }
+    }
+    const float P = combine8(q);
+    float pre[8], suf[8], acc = 1.f;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) { pre[m] = acc; acc = acc * (1.f - q[m]); }
+    acc = 1.f;
+#pragma unroll
+    for (int m = 7; m >= 0; --m) { suf[m] = acc; acc = acc * (1.f - q[m]); }
+    gl[0] = gl[1] = gl[2] = gl[3] = 0.f;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const float sc = pre[m] * suf[m] * (J.c * (1.f - q[m] * q[m]));
+#pragma unroll
+        for (int d = 0; d < 4; ++d) gl[d] = gl[d] + sc * dx[m][d];
+    }
+    return P;
+}
+
+template <int NWAVE>
 __device__ __forceinline__ int block_exscan(int v, int* sWave, int* total) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int x = v;
@@ -135,7 +194,7 @@ __device__ __forceinline__ int block_exscan(int v, int* sWave, int* total) {
     __syncthreads();
     int pre = 0, tot = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < NWAVE; ++k) {
         const int s = sWave[k];
         if (k < wv) pre += s;
         tot += s;
@@ -158,22 +217,23 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 
 // --------------------------------------------------------------- main step
 
-template <int TR, int TC, int KM, bool ADJ>
-__global__ void __launch_bounds__(256)
+template <int TR, int TC, int KM, bool ADJ, int NT>
+__global__ void __launch_bounds__(NT)
 k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, int32_t ntiles,
        int32_t parity, int32_t t_off, int32_t ksteps, int32_t skip,
-       const float* __restrict__ lam, unsigned long long* __restrict__ stats) {
+       const float* __restrict__ lam, Rings rings, unsigned long long* __restrict__ stats) {
     constexpr int RR = TR + 2 * KM, RC = TC + 2, NW = RR * RC;
-    constexpr int WPT = (NW + 255) / 256;
+    constexpr int WPT = (NW + NT - 1) / NT;
+    constexpr int NWAVE = NT / 64;
     constexpr int LCAP = NW * 32;  // worst case: every cell of the region has a trial
     static_assert(NW * 32 < 65536, "trial list entries are 16-bit");
     static_assert(KM <= TR && KM <= 32, "halo deeper than a tile");
 
     __shared__ uint32_t sB[2][NW], sD[2][NW], sU[NW], sR[NW];
     __shared__ uint16_t sL[LCAP];
-    __shared__ int sWave[4];
+    __shared__ int sWave[NWAVE];
     __shared__ int sFlag;
-    __shared__ double sG[ADJ ? 4 * 4 : 1];
+    __shared__ double sG[ADJ ? NWAVE * 4 : 1];
 
     const int tid = threadIdx.x;
     const int g = xcd_tile(blockIdx.x, gridDim.x);
@@ -205,7 +265,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     }
     if (!need) {
         if (!(fin[lt] & 2)) {  // bring the other buffer up to date once
-            for (int w = tid; w < TR * TC; w += 256) {
+            for (int w = tid; w < TR * TC; w += NT) {
                 const int gr = trow * TR + w / TC, gw = tcol * TC + w % TC;
                 if (gr < H && gw < pitch) {
                     const int64_t o = (int64_t)gr * pitch + gw;
@@ -224,7 +284,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     uint32_t origB[WPT], origD[WPT];
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
-        const int w = tid + i * 256;
+        const int w = tid + i * NT;
         origB[i] = origD[i] = 0;
         if (w < NW) {
             const int lr = w / RC, lc = w - (w / RC) * RC;
@@ -263,7 +323,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         int cnt = 0;  // continue count | ignition count << 16
 #pragma unroll
         for (int i = 0; i < WPT; ++i) {
-            const int w = tid + i * 256;
+            const int w = tid + i * NT;
             mc[i] = mi[i] = 0;
             if (w < NW) {
                 const int lr = w / RC, lc = w - (w / RC) * RC;
@@ -282,7 +342,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             }
         }
         int tot;
-        const int off = block_exscan(cnt, sWave, &tot);
+        const int off = block_exscan<NWAVE>(cnt, sWave, &tot);
         const int tot_c = tot & 0xFFFF, tot_i = tot >> 16;
 
         // compacted trial list: continue entries first, then ignition entries
@@ -290,7 +350,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             int oc = off & 0xFFFF, oi = tot_c + (off >> 16);
 #pragma unroll
             for (int i = 0; i < WPT; ++i) {
-                const int w = tid + i * 256;
+                const int w = tid + i * NT;
                 uint32_t m = mc[i];
                 while (m) {
                     const int bit = __ffs(m) - 1;
@@ -307,16 +367,85 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         }
         __syncthreads();
 
-        // Continue trials take one lane each.  Ignition trials take an aligned
-        // group of 8 lanes (one per neighbour slot: the trial's gathers are
-        // issued together and its per-edge transcendental chains run side by
-        // side) when all trials of the step fit in one pass of the work-group;
-        // otherwise one lane each, walking its 8 slots.  Both use the same
-        // Eq. 9 pairing tree, so p_ignite is bit-identical either way.
-        const bool wide = tot_c + 8 * tot_i <= 256;
+        const int ntr = tot_c + tot_i;
+        if constexpr (!ADJ) {
+            // Forward: p_ignite of an ignition trial is Eq. 9 over the q8 entries
+            // of its burning neighbour slots (the Eq. 2-5 work was done for
+            // every edge at the start of the run).  Each lane takes up to 4
+            // trials per pass and issues all of their gathers before deciding.
+            constexpr int R = 4;
+            const float4* q8v = reinterpret_cast<const float4*>(J.q8);
+            for (int k0 = 0; k0 < ntr; k0 += R * NT) {
+                int ent[R];
+                float4 qa[R], qb[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = k0 + r * NT + tid;
+                    ent[r] = k < ntr ? (int)sL[k] : -1;
+                    qa[r] = qb[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (k >= tot_c && k < ntr) {
+                        const int w = ent[r] >> 5, bit = ent[r] & 31;
+                        const int lr = w / RC, lc = w - (w / RC) * RC;
+                        const int64_t j = (int64_t)(r0 + lr) * J.W + ((w0 + lc) * 32 + bit);
+                        qa[r] = q8v[2 * j];
+                        qb[r] = q8v[2 * j + 1];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int k = k0 + r * NT + tid;
+                    if (k >= ntr) continue;
+                    const int w = ent[r] >> 5, bit = ent[r] & 31;
+                    const int lr = w / RC, lc = w - (w / RC) * RC;
+                    const int64_t j = (int64_t)(r0 + lr) * J.W + ((w0 + lc) * 32 + bit);
+                    const bool interior = lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC;
+                    uint32_t rw0, rw1;
+                    philox_w01((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, scen,
+                               k0s, k1s, rw0, rw1);
+                    if (k < tot_c) {  // burning: continue trial
+                        if (u24(rw1) < J.p_continue) {
+                            atomicOr(&sR[w], 1u << bit);
+                        } else if (interior && J.tout) {
+                            J.tout[j] = t;
+                        }
+                        if (interior) ++n_trials;
+                        continue;
+                    }
+                    const float qs[8] = {qa[r].x, qa[r].y, qa[r].z, qa[r].w,
+                                         qb[r].x, qb[r].y, qb[r].z, qb[r].w};
+                    float q[8];
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) {
+                        int dr, dc;
+                        slot_dir(m, dr, dc);
+                        const int cl = lc * 32 + bit + dc;
+                        const bool burn = cl >= 0 && cl < RC * 32 &&
+                                          ((cB[(lr + dr) * RC + (cl >> 5)] >> (cl & 31)) & 1u);
+                        q[m] = burn ? qs[m] : 0.f;
+                    }
+                    const float P = combine8(q);
+                    const float u = u24(rw0);
+                    if (u < P) {
+                        atomicOr(&sR[w], 1u << bit);
+                        if (interior && J.yhat) J.yhat[j] = P;
+                        if (interior && J.tign) J.tign[j] = t;
+                    }
+                    if (interior) {
+                        ++n_trials;
+                        if (fabsf(u - P) <= kTieEps) ++n_ties;
+                    }
+                }
+            }
+        } else {
+        // Adjoint recompute: the same p_ignite (same Eq. 2-5 function on the
+        // same inputs, same Eq. 9 tree) plus its derivatives.  Continue trials
+        // take one lane each.  Ignition trials take an aligned group of 8 lanes
+        // (one per neighbour slot, the per-edge chains side by side) when all
+        // trials of the step fit in one pass; otherwise one lane each.
+        const bool wide = tot_c + 8 * tot_i <= NT;
         const int base_i = wide ? ((tot_c + 7) & ~7) : tot_c;
         const int nslots = base_i + (wide ? 8 : 1) * tot_i;
-        for (int k0 = 0; k0 < nslots; k0 += 256) {
+        for (int k0 = 0; k0 < nslots; k0 += NT) {
             const int k = k0 + tid;
             if (k >= nslots) continue;
             const bool cont = k < tot_c;
@@ -341,86 +470,47 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                        ((cB[(lr + dr) * RC + (cl >> 5)] >> (cl & 31)) & 1u);
             };
             const float4 rec = J.rec[j];
-            const float Ej = J.elev[j];
             float P;
             float gl[4] = {0.f, 0.f, 0.f, 0.f};
             if (wide) {
                 int dr, dc;
                 slot_dir(e, dr, dc);
                 const bool burn = burning(dr, dc);
-                const float Ei = burn ? J.elev[j + (int64_t)dr * J.W + dc] : 0.f;
+                const float th = J.th8[j * 8 + e];
                 Edge ed{0.f, 0.f, 0.f, 0.f, 0.f};
-                if (burn) ed = edge_terms(J, rec, Ej, Ei, dr, dc);
+                if (burn) ed = edge_terms(J, rec, th, dr, dc);
                 P = combine8_lanes(ed.q);
-                if (ADJ) {
-                    // d p_ignite / d q_e = prod over the other slots of (1 - q)
-                    const float om = 1.f - ed.q;
-                    const int g0 = threadIdx.x & 56;
-                    float prod = 1.f;
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) {
-                        const float o = __shfl(om, g0 + m, 64);
-                        prod = prod * (m == e ? 1.f : o);
-                    }
-                    const float sc = prod * (J.c * (1.f - ed.q * ed.q));
-                    gl[0] = sc * (rec.x * ed.ez);       // dx/dp_h = F e^z
-                    gl[1] = sc * (ed.x * ed.th);        // dx/da   = x theta_s
-                    gl[2] = sc * (ed.x * rec.y);        // dx/dc1  = x V
-                    gl[3] = sc * (ed.x * ed.vterm);     // dx/dc2  = x V (cos - 1)
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        gl[m] = gl[m] + __shfl_xor(gl[m], 1, 64);
-                        gl[m] = gl[m] + __shfl_xor(gl[m], 2, 64);
-                        gl[m] = gl[m] + __shfl_xor(gl[m], 4, 64);
-                    }
-                }
-            } else {
-                float q[8], dx[8][4];
+                // d p_ignite / d q_e = prod over the other slots of (1 - q)
+                const float om = 1.f - ed.q;
+                const int g0 = threadIdx.x & 56;
+                float prod = 1.f;
 #pragma unroll
                 for (int m = 0; m < 8; ++m) {
-                    int dr, dc;
-                    slot_dir(m, dr, dc);
-                    q[m] = 0.f;
-                    dx[m][0] = dx[m][1] = dx[m][2] = dx[m][3] = 0.f;
-                    if (burning(dr, dc)) {
-                        const Edge ed =
-                            edge_terms(J, rec, Ej, J.elev[j + (int64_t)dr * J.W + dc], dr, dc);
-                        q[m] = ed.q;
-                        if (ADJ) {
-                            dx[m][0] = rec.x * ed.ez;
-                            dx[m][1] = ed.x * ed.th;
-                            dx[m][2] = ed.x * rec.y;
-                            dx[m][3] = ed.x * ed.vterm;
-                        }
-                    }
+                    const float o = __shfl(om, g0 + m, 64);
+                    prod = prod * (m == e ? 1.f : o);
                 }
-                P = combine8(q);
-                if (ADJ) {
-                    float pre[8], suf[8], acc = 1.f;
+                const float sc = prod * (J.c * (1.f - ed.q * ed.q));
+                gl[0] = sc * (rec.x * ed.ez);       // dx/dp_h = F e^z
+                gl[1] = sc * (ed.x * ed.th);        // dx/da   = x theta_s
+                gl[2] = sc * (ed.x * rec.y);        // dx/dc1  = x V
+                gl[3] = sc * (ed.x * ed.vterm);     // dx/dc2  = x V (cos - 1)
 #pragma unroll
-                    for (int m = 0; m < 8; ++m) { pre[m] = acc; acc = acc * (1.f - q[m]); }
-                    acc = 1.f;
-#pragma unroll
-                    for (int m = 7; m >= 0; --m) { suf[m] = acc; acc = acc * (1.f - q[m]); }
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) {
-                        const float sc = pre[m] * suf[m] * (J.c * (1.f - q[m] * q[m]));
-#pragma unroll
-                        for (int d = 0; d < 4; ++d) gl[d] = gl[d] + sc * dx[m][d];
-                    }
+                for (int m = 0; m < 4; ++m) {
+                    gl[m] = gl[m] + __shfl_xor(gl[m], 1, 64);
+                    gl[m] = gl[m] + __shfl_xor(gl[m], 2, 64);
+                    gl[m] = gl[m] + __shfl_xor(gl[m], 4, 64);
                 }
+            } else {
+                P = pignite_grad(J, j, burning, gl);
             }
             if (e == 0) {
                 const float u = u24(rw0);
                 if (u < P) {
                     atomicOr(&sR[w], 1u << bit);
-                    if (interior) {
-                        if (J.yhat) J.yhat[j] = P;
-                        if (ADJ) {
-                            const float lj = lam[J.lam_off + j];
+                    if (interior && attached(rings, t)) {
+                        const float lj = lam[J.lam_off + j];
 #pragma unroll
-                            for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj * gl[m]);
-                        }
+                        for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj * gl[m]);
                     }
                 }
                 if (interior) {
@@ -429,12 +519,13 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 }
             }
         }
+        }
         __syncthreads();
 
         // combine: burning' = successful trials; burned' = burned | burnt out
 #pragma unroll
         for (int i = 0; i < WPT; ++i) {
-            const int w = tid + i * 256;
+            const int w = tid + i * NT;
             if (w < NW) {
                 const int lr = w / RC;
                 if (lr >= lo && lr < hi) {
@@ -452,7 +543,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     bool anyB = false, changed = false;
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
-        const int w = tid + i * 256;
+        const int w = tid + i * NT;
         if (w < NW) {
             const int lr = w / RC, lc = w - (w / RC) * RC;
             if (lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC) {
@@ -485,9 +576,11 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         const int f = sFlag;
         fout[lt] = (uint8_t)(((f & 1) ? 1 : 0) | ((f & 2) ? 0 : 2));
         if (ADJ) {
-            for (int m = 0; m < 4; ++m)
-                J.gpart[(int64_t)g * 4 + m] +=
-                    ((sG[0 * 4 + m] + sG[1 * 4 + m]) + (sG[2 * 4 + m] + sG[3 * 4 + m]));
+            for (int m = 0; m < 4; ++m) {
+                double acc = 0.0;
+                for (int v = 0; v < NWAVE; ++v) acc += sG[v * 4 + m];
+                J.gpart[(int64_t)g * 4 + m] += acc;
+            }
         }
     }
     if (stats) {
@@ -504,6 +597,63 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         }
         if (tid == 0) atomicAdd(&stats[0], 1ull);
     }
+}
+
+// ------------------------------------------------- per-edge tables (Eq. 1-5)
+
+// th8[j][m] = Eq. 1 slope from neighbour slot m up to cell j (0 where the
+// neighbour is outside the grid; such slots never burn).
+__global__ void __launch_bounds__(256)
+k_slopes(DevScen J, float* __restrict__ th8) {
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= J.W) return;
+    const int64_t j = (int64_t)r * J.W + c;
+    const float Ej = J.elev[j];
+    float th[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        int dr, dc;
+        slot_dir(m, dr, dc);
+        const int rr = r + dr, cc = c + dc;
+        th[m] = 0.f;
+        if (rr >= 0 && rr < J.H && cc >= 0 && cc < J.W)
+            th[m] = slope_deg(J, Ej, J.elev[(int64_t)rr * J.W + cc], dr, dc);
+    }
+    float4* o = reinterpret_cast<float4*>(th8 + j * 8);
+    o[0] = make_float4(th[0], th[1], th[2], th[3]);
+    o[1] = make_float4(th[4], th[5], th[6], th[7]);
+}
+
+// q8[j][m] = f_p(p_propagate) of the edge from slot m into cell j (Eq. 2-5)
+// for every cell of every scenario; one flat grid, blocks mapped to scenarios
+// through the prefix sums of their cell counts.
+__global__ void __launch_bounds__(256)
+k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, int32_t n) {
+    const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gi >= cell0[n]) return;
+    int lo = 0, hi = n;   // scenario s with cell0[s] <= gi < cell0[s + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cell0[mid] <= gi) lo = mid; else hi = mid;
+    }
+    const int s = lo;
+    const DevScen& J = jobs[s];
+    const int64_t j = gi - cell0[s];
+    const float4 rec = J.rec[j];
+    const float4* tv = reinterpret_cast<const float4*>(J.th8 + j * 8);
+    const float4 ta = tv[0], tb = tv[1];
+    const float th[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
+    float q[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        int dr, dc;
+        slot_dir(m, dr, dc);
+        q[m] = edge_terms(J, rec, th[m], dr, dc).q;
+    }
+    float4* o = reinterpret_cast<float4*>(J.q8 + j * 8);
+    o[0] = make_float4(q[0], q[1], q[2], q[3]);
+    o[1] = make_float4(q[4], q[5], q[6], q[7]);
 }
 
 // ------------------------------------------------------------- prologue
@@ -559,7 +709,8 @@ k_prologue(int32_t H, int32_t W, int32_t pitch, const float* __restrict__ p_veg,
 
 __global__ void __launch_bounds__(256)
 k_init_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ ign,
-             uint32_t* __restrict__ planes, float* __restrict__ yhat) {
+             uint32_t* __restrict__ planes, float* __restrict__ yhat,
+             int32_t* __restrict__ tign, int32_t* __restrict__ tout) {
     const int r = blockIdx.y;
     const int c = blockIdx.x * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -568,6 +719,8 @@ k_init_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ ig
         const int64_t j = (int64_t)r * W + c;
         burning = ign[j] != 0;
         if (yhat) yhat[j] = burning ? 1.f : 0.f;
+        if (tign) tign[j] = burning ? 0 : INT_MAX;
+        if (tout) tout[j] = INT_MAX;
     }
     const unsigned long long mb = __ballot(burning);
     const int wbase = (blockIdx.x * 256 + (threadIdx.x & ~63)) >> 5;
@@ -580,6 +733,52 @@ k_init_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ ig
             planes[PW + o] = 0u;
         }
     }
+}
+
+// Time-map adjoint: for every cell j that ignited at step t_j >= 1 of an
+// attached step, rebuild its burning neighbours at t_j - 1 from the maps
+// (neighbour i burned then iff tign_i <= t_j - 1 < tout_i) and add
+// lambda_j * d p_ignite_j / d theta.  One block covers cells of one scenario;
+// gpart[block] receives the block's FP64 sum in a fixed order.
+__global__ void __launch_bounds__(256)
+k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0, int32_t n,
+               const float* __restrict__ lam, Rings rings, double* __restrict__ gpart) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = n;   // scenario s with bl0[s] <= b < bl0[s + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (bl0[mid] <= b) lo = mid; else hi = mid;
+    }
+    const DevScen& J = jobs[lo];
+    const int64_t j = (int64_t)(b - bl0[lo]) * 256 + threadIdx.x;
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    if (j < (int64_t)J.H * J.W) {
+        const int tj = J.tign[j];
+        if (tj >= 1 && tj <= rings.T && attached(rings, tj)) {
+            const int r = (int)(j / J.W), c = (int)(j - (int64_t)r * J.W);
+            auto nb = [&](int dr, int dc) -> bool {
+                const int rr = r + dr, cc = c + dc;
+                if (rr < 0 || rr >= J.H || cc < 0 || cc >= J.W) return false;
+                const int64_t i = (int64_t)rr * J.W + cc;
+                return J.tign[i] <= tj - 1 && tj - 1 < J.tout[i];
+            };
+            float gl[4];
+            pignite_grad(J, j, nb, gl);
+            const float lj = lam[J.lam_off + j];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) g[m] = (double)(lj * gl[m]);
+        }
+    }
+    __shared__ double sh[4][256];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] = g[m];
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d)
+            for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] += sh[m][threadIdx.x + d];
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) gpart[(int64_t)b * 4 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 __global__ void __launch_bounds__(256)
@@ -895,10 +1094,32 @@ hipError_t launch_prologue(hipStream_t st, const DevScen* /*d_job*/, const DevSc
     return hipGetLastError();
 }
 
+hipError_t launch_slopes(hipStream_t st, const DevScen& J, float* th8) {
+    hipLaunchKernelGGL(k_slopes, cell_grid(J.H, J.W), dim3(256), 0, st, J, th8);
+    return hipGetLastError();
+}
+
+hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
+                         int64_t total_cells) {
+    if (total_cells <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_qtable, dim3((unsigned)((total_cells + 255) / 256)), dim3(256), 0, st,
+                       d_jobs, d_cell0, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_state(hipStream_t st, const DevScen& J, const uint8_t* ign,
-                             uint32_t* planes, float* yhat) {
+                             uint32_t* planes, float* yhat, int32_t* tign, int32_t* tout) {
     hipLaunchKernelGGL(k_init_state, cell_grid(J.H, J.pitch * 32), dim3(256), 0, st, J.H, J.W,
-                       J.pitch, ign, planes, yhat);
+                       J.pitch, ign, planes, yhat, tign, tout);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_tmap(hipStream_t st, const DevScen* d_jobs, const int32_t* d_bl0,
+                               int32_t n, int32_t nblocks, const float* lam, Rings rings,
+                               double* gpart) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adjoint_tmap, dim3(nblocks), dim3(256), 0, st, d_jobs, d_bl0, n, lam,
+                       rings, gpart);
     return hipGetLastError();
 }
 
@@ -959,8 +1180,12 @@ hipError_t launch_loss(hipStream_t st, int32_t H, int32_t W, const float* yhat,
 // ------------------------------------------------- step shape dispatch table
 
 namespace {
+#ifndef FS_STEP_THREADS
+#define FS_STEP_THREADS 256
+#endif
+constexpr int kStepThreads = FS_STEP_THREADS;
 using StepFn = void (*)(const DevScen*, const int32_t*, int32_t, int32_t, int32_t, int32_t,
-                        int32_t, const float*, unsigned long long*);
+                        int32_t, const float*, Rings, unsigned long long*);
 
 struct StepEntry {
     int tr, tc, km;
@@ -968,9 +1193,9 @@ struct StepEntry {
     StepFn fn;
 };
 
-#define FS_SHAPE(TR, TC, KM)                          \
-    {TR, TC, KM, false, &k_step<TR, TC, KM, false>}, \
-    {TR, TC, KM, true, &k_step<TR, TC, KM, true>},
+#define FS_SHAPE(TR, TC, KM)                                   \
+    {TR, TC, KM, false, &k_step<TR, TC, KM, false, kStepThreads>}, \
+    {TR, TC, KM, true, &k_step<TR, TC, KM, true, kStepThreads>},
 
 const StepEntry kSteps[] = {
     FS_SHAPE(16, 4, 1) FS_SHAPE(16, 4, 4) FS_SHAPE(16, 4, 8) FS_SHAPE(16, 4, 16)
@@ -1003,12 +1228,12 @@ int step_shapes(TileShape* out, int max) {
 hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_jobs,
                        const int32_t* d_tile_job, int32_t ntiles, int32_t parity,
                        int32_t t_off, int32_t ksteps, int32_t skip, const float* lam,
-                       unsigned long long* d_stats) {
+                       Rings rings, unsigned long long* d_stats) {
     const StepEntry* e = find_step(sh, adj);
     if (!e) return hipErrorInvalidValue;
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(e->fn, dim3(ntiles), dim3(256), 0, st, d_jobs, d_tile_job, ntiles,
-                       parity, t_off, ksteps, skip, lam, d_stats);
+    hipLaunchKernelGGL(e->fn, dim3(ntiles), dim3(kStepThreads), 0, st, d_jobs, d_tile_job, ntiles,
+                       parity, t_off, ksteps, skip, lam, rings, d_stats);
     return hipGetLastError();
 }
 

@@ -186,6 +186,13 @@ class Sim:
             self._check(self._lib.sim_accumulator(self._h, s, _ptr(out[a:b])))
         return out
 
+    def set_adjoint(self, method: str = "checkpoint", rings=None):
+        """method: "checkpoint" (recompute segments) or "timemap"; rings:
+        None (every step attached) or (r_first, r_between, r_last)."""
+        m = {"checkpoint": _abi.SIM_ADJ_CHECKPOINT, "timemap": _abi.SIM_ADJ_TIMEMAP}[method]
+        rf, rb, rl = (-1, 0, 0) if rings is None else (int(x) for x in rings)
+        self._check(self._lib.sim_set_adjoint(self._h, m, rf, rb, rl))
+
     def adjoint(self, dL_dyhat: torch.Tensor) -> torch.Tensor:
         lam = dL_dyhat.to(device=self.device, dtype=torch.float32).contiguous().view(-1)
         if lam.numel() != int(self.offsets[-1]):

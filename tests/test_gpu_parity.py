@@ -414,3 +414,46 @@ def test_calibrate_mechanics_and_descent(Sim):
     step = 1e-3 * g0 / np.linalg.norm(g0)
     L1, _ = loss_grad(th - step)
     assert L1 < L0, (L0, L1, g0)
+
+
+# ------------------------------------------------ time-map adjoint, rings
+
+def ring_attached(t, T, first, between, last):
+    """The step-ring attach set: steps 1..first, the last `last` steps and
+    `between` steps spread evenly in between (round half up)."""
+    if first < 0:
+        return True
+    if t <= first or t > T - last:
+        return True
+    span = T - first - last
+    return any(t == first + (k * span + (between + 1) // 2) // (between + 1)
+               for k in range(1, between + 1))
+
+
+@pytest.mark.parametrize("rings", [None, (3, 4, 5), (0, 2, 1)])
+def test_adjoint_methods_and_step_rings_match_oracle(Sim, rings):
+    import torch
+    T = 40
+    cases = [calib_case(64, 96, 51, T), calib_case(45, 77, 52, T)]
+    scs = [c[0] for c in cases]
+    sim = Sim(scs, calib=True, T_max=T, ckpt_every=8)
+    sim.run(T)
+    rng = np.random.default_rng(3)
+    lams = [rng.standard_normal((s.H, s.W)).astype(np.float32) for s in scs]
+    lam_t = torch.from_numpy(np.concatenate([l.ravel() for l in lams]))
+    grads = {}
+    for method in ("checkpoint", "timemap"):
+        sim.set_adjoint(method, rings)
+        grads[method] = sim.adjoint(lam_t).cpu().numpy()
+    np.testing.assert_allclose(grads["timemap"], grads["checkpoint"], rtol=1e-5,
+                               atol=1e-6 * np.abs(grads["checkpoint"]).max())
+    for b, s in enumerate(scs):
+        r = oracle.run(s, T, want_tstep=True)
+        assert np.array_equal(gstate(sim, b), r["S"])
+        att = np.vectorize(lambda t: t >= 1 and ring_attached(
+            int(t), T, *(rings if rings else (-1, 0, 0))))(r["tstep"])
+        g = oracle.grad(s, T, np.where(att, lams[b], 0.0).astype(np.float64))
+        scale = np.abs(g).max()
+        for method in grads:
+            gg = grads[method][b]
+            assert np.all(np.abs(gg - g) <= 1e-4 * np.abs(g) + 1e-5 * scale), (method, gg, g)
