@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # state, F = (1+p_veg)(1+p_den), elevation, wind speed and direction, and
 # writes 2 bits): 0.5 + 4 + 4 + 8.
 DENSE_BYTES_PER_CELL_STEP = 16.5
-DEFAULT_EXEC = dict(tile_rows=16, tile_words=4, depth=16, skip=True)
+DEFAULT_EXEC = dict(tile_rows=32, tile_words=4, depth=16, skip=True)
 PLAIN_EXEC = dict(tile_rows=16, tile_words=8, depth=1, skip=False)
 
 
@@ -93,6 +93,7 @@ def summarize_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, cop
     fetch_b = sum(fk) / len(fk) * 1024.0 * f_fetch
     write_b = sum(wk) / len(wk) * 1024.0 * f_write
     out = {"kernel_regex": kernel_regex, "kernel_source_sha": kernel_source_hash(),
+           "exec": dict(DEFAULT_EXEC),
            "dispatches": [len(fk), len(wk)],
            "fetch_KiB_per_dispatch": sum(fk) / len(fk), "write_KiB_per_dispatch": sum(wk) / len(wk),
            "copy_scale": {"fetch": f_fetch, "write": f_write, "copy_bytes": copy_bytes},
@@ -149,9 +150,12 @@ def leg_main(args, torch, Sim, synth):
                  "per launch; the kernel reads fields only for cells with a trial",
     }
     tr = load_traffic("k_step_config2")
+    if tr and tr.get("exec") != DEFAULT_EXEC:
+        tr = None
     if tr:
-        roof["traffic"] = tr["bytes_per_launch"]
+        roof["traffic"] = round(tr["bytes_per_launch"])
         roof["traffic_GBps"] = round(tr["bytes_per_launch"] / launch_s / 1e9, 1)
+        roof["traffic_frac"] = round(tr["bytes_per_launch"] / launch_s / 1e9 / HBM_PEAK_GBS, 4)
     # work actually done: tiles processed and trials (separate counting run)
     st = Sim([s], exec=DEFAULT_EXEC, stats=True)
     st.run(T)
@@ -232,11 +236,16 @@ def leg_calib(args, torch, Sim, synth):
 
     K = max(2, args.steps)
     wall, gpu = timed(grad_step, K, 1, torch)
+    sim.set_adjoint("timemap")
+    wall_tm, _ = timed(grad_step, K, 1, torch)
     cells = 1024 * 1024 * n
     return {
         "metric": "calibration grad-steps/s", "value": round(K / wall, 3),
+        "adjoint": "checkpoint every 20 steps, segments recomputed",
         "ms_per_grad_step": round(wall / K * 1e3, 2),
         "G_cell_steps_per_s": round(2 * cells * T * K / wall / 1e9, 3),
+        "timemap_adjoint": {"value": round(K / wall_tm, 3),
+                            "ms_per_grad_step": round(wall_tm / K * 1e3, 2)},
         "config": {"workload": "64 scenarios 1024x1024, 200 steps, checkpoints every 20, "
                                "BCE loss, AdamW lr 5e-3 with clamps",
                    "exec": DEFAULT_EXEC},
@@ -248,13 +257,9 @@ def leg_batched(args, torch, Sim, synth):
     log("batched: generating", n, "scenarios")
     scs = [synth.config3_scenario(b, T=T) for b in range(n)]
     sim = Sim(scs)
-    if args.autotune:
-        sim.run(150)
-        ex = sim.autotune(16)
-        sim.reset()
-    else:
-        ex = dict(DEFAULT_EXEC)
-        sim.set_exec(**ex)
+    sim.run(150)
+    ex = sim.autotune(16)
+    sim.reset()
 
     def run():
         sim.reset()
@@ -291,8 +296,9 @@ def main():
     ap.add_argument("--exec", default=None, metavar="TR,TC,DEPTH,SKIP",
                     help="execution shape of the main leg (tile rows, tile words, steps "
                          "per launch, skip 0/1)")
-    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
-                    help="keep the default (or --exec) shape instead of autotuning")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the main leg's shape on a mid-run state (the batched "
+                         "leg always autotunes)")
     ap.add_argument("--copy-ref", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (reference "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -323,7 +329,6 @@ def main():
     if args.exec:
         tr, tc, dp, sk = (int(x) for x in args.exec.split(","))
         DEFAULT_EXEC.update(tile_rows=tr, tile_words=tc, depth=dp, skip=bool(sk))
-        args.autotune = False
 
     import torch
     import synth
