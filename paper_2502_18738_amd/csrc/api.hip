@@ -18,7 +18,7 @@
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMinTR = 8, kMinTC = 2;  // smallest whitelisted tile -> flag capacity
+constexpr int kMinTR = 8, kMinTC = 1;  // smallest whitelisted tile -> flag capacity
 constexpr int kMaxN = 65536;
 constexpr int kMaxSide = 1 << 16;
 const float kC = 1.1486328125f;        // f_p constant of Eq. 5 / 8, FP32
@@ -37,7 +37,8 @@ struct ScenLayout {
 
 struct Layout {
     size_t err, stats, box, part, jobs, tile_job, adj_jobs, adj_tile_job, gpart, ranges, lam,
-        cell0, bl0, gpart_tmap, total;
+        cell0, bl0, gpart_tmap, masks, adj_masks, total;
+    int32_t mask_words, adj_mask_words;
     int64_t total_cells;
     int32_t tmap_blocks;
     std::vector<ScenLayout> s;
@@ -76,6 +77,8 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
     }
     L->max_tiles_total = tiles;
     L->tile_job = take(sizeof(int32_t) * (size_t)tiles);
+    L->mask_words = (int32_t)cdiv(tiles, 64);
+    L->masks = take(3 * 8 * (size_t)L->mask_words);
     for (int i = 0; i < n; ++i) {
         ScenLayout& s = L->s[i];
         const int64_t cells = (int64_t)d[i].H * d[i].W;
@@ -97,6 +100,8 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         }
     }
     L->adj_jobs = L->adj_tile_job = L->gpart = L->ranges = L->lam = L->bl0 = L->gpart_tmap = 0;
+    L->adj_masks = 0;
+    L->adj_mask_words = 0;
     L->tmap_blocks = 0;
     L->adj_max_tiles_total = 0;
     for (int k = 0; k < 2; ++k) {
@@ -107,6 +112,8 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         L->adj_jobs = take(sizeof(fs::DevScen) * (size_t)n * L->nseg);
         L->adj_max_tiles_total = tiles * L->nseg;
         L->adj_tile_job = take(sizeof(int32_t) * (size_t)L->adj_max_tiles_total);
+        L->adj_mask_words = (int32_t)cdiv(L->adj_max_tiles_total, 64);
+        L->adj_masks = take(3 * 8 * (size_t)L->adj_mask_words);
         L->gpart = take(4 * sizeof(double) * (size_t)L->adj_max_tiles_total);
         L->ranges = take(sizeof(int32_t) * (size_t)(n + 1));
         int64_t cells = 0;
@@ -200,12 +207,14 @@ struct sim_handle {
     sim_exec ex{};
     fs::TileShape sh{};
     int parity = 0, step = 0;
+    int lidx = 0;                   // launches since the worklist was last rebuilt
+    int grid_max = 1024;            // work-groups of a worklist launch
     unsigned long long launches = 0;
     int64_t max_words = 0;
     std::string err;
     // captured launch sequences of sim_run, keyed by where they start
     struct Graph {
-        int step, T, parity, ntiles;
+        int step, T, parity, ntiles, lmod;
         sim_exec ex;
         hipGraphExec_t exec;
     };
@@ -231,6 +240,7 @@ struct sim_handle {
     int32_t* d_tile_job() { return reinterpret_cast<int32_t*>(ws + L.tile_job); }
     int* d_err() { return reinterpret_cast<int*>(ws + L.err); }
     unsigned long long* d_stats() { return reinterpret_cast<unsigned long long*>(ws + L.stats); }
+    unsigned long long* d_masks() { return reinterpret_cast<unsigned long long*>(ws + L.masks); }
     bool calib() const { return flags & SIM_F_CALIB; }
 
     int fail(int code, const char* fmt, ...) {
@@ -257,6 +267,8 @@ fs::TileShape shape_of(const sim_exec& e) {
     return fs::TileShape{e.tile_rows, e.tile_words, km};
 }
 
+int refresh_worklist(sim_handle* h, bool dup);
+
 // Recompute tile grids and the tile -> job table of the forward jobs.
 int rebuild_tiles(sim_handle* h) {
     int32_t g = 0;
@@ -282,8 +294,23 @@ int rebuild_tiles(sim_handle* h) {
     // the host vectors are reused by later calls: wait for the copies
     rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
     if (rc) return rc;
-    return h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles,
-                                        h->parity, h->sh), "flags init");
+    return refresh_worklist(h, true);
+}
+
+// After any change of the state or of the tiling: both ping-pong buffers
+// equal to the current state, flags recomputed and the first worklist built.
+int refresh_worklist(sim_handle* h, bool dup) {
+    int rc = SIM_OK;
+    if (dup)
+        rc = h->hip(fs::launch_dup_planes(h->st, h->d_jobs(), h->n, h->parity, h->max_words),
+                    "copy state");
+    if (!rc) rc = h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles,
+                                               h->parity, h->sh), "flags init");
+    if (!rc) rc = h->hip(fs::launch_mask_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles,
+                                              h->parity, h->d_masks(), h->L.mask_words),
+                         "worklist init");
+    h->lidx = 0;
+    return rc;
 }
 
 int save_ckpt(sim_handle* h, int slot) {
@@ -301,8 +328,7 @@ int reset_state(sim_handle* h) {
                                               J.yhat, J.tign, J.tout), "init state");
         if (rc) return rc;
     }
-    int rc = h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles, 0,
-                                          h->sh), "flags init");
+    int rc = refresh_worklist(h, false);   // init_state wrote both buffers
     if (rc) return rc;
     rc = h->hip(hipMemsetAsync(h->d_stats(), 0, 4 * sizeof(unsigned long long), h->st),
                 "clear stats");
@@ -367,6 +393,13 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
     }
     h->ws = static_cast<char*>(workspace);
 
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            cus > 0)
+            h->grid_max = 4 * cus;
+    }
     // default execution shape
     int32_t max_pitch = 0;
     for (const auto& s : h->L.s) max_pitch = std::max(max_pitch, s.pitch);
@@ -479,7 +512,7 @@ int sim_set_exec(sim_handle* h, const sim_exec* e) {
     h->ex.skip = e->skip ? 1 : 0;
     const bool same = sh.tr == h->sh.tr && sh.tc == h->sh.tc;
     h->sh = sh;
-    if (same) return SIM_OK;
+    if (same) return refresh_worklist(h, true);
     return rebuild_tiles(h);
 }
 
@@ -498,10 +531,19 @@ int enqueue_run(sim_handle* h, hipStream_t st, int T, unsigned long long* stats)
     while (T > 0) {
         int k = std::min(h->ex.depth, T);
         if (h->calib()) k = std::min(k, h->ckpt_every - h->step % h->ckpt_every);
+        fs::Sched sc{nullptr, nullptr, nullptr, h->L.mask_words};
+        if (h->ex.skip) {
+            unsigned long long* m = h->d_masks();
+            const int64_t nw = h->L.mask_words;
+            sc.in = m + nw * (h->lidx % 3);
+            sc.out = m + nw * ((h->lidx + 1) % 3);
+            sc.clear = m + nw * ((h->lidx + 2) % 3);
+        }
         int rc = h->hip(fs::launch_step(st, h->sh, false, h->d_jobs(), h->d_tile_job(), h->ntiles,
                                         h->parity, h->step, k, h->ex.skip, nullptr,
-                                        fs::Rings{-1, 0, 0, 0}, stats),
+                                        fs::Rings{-1, 0, 0, 0}, sc, h->grid_max, stats),
                         "step kernel");
+        ++h->lidx;
         if (rc) return rc;
         ++h->launches;
         h->parity ^= 1;
@@ -540,7 +582,7 @@ bool same_exec(const sim_exec& a, const sim_exec& b) {
 int run_graph(sim_handle* h, int T) {
     for (auto& g : h->graphs) {
         if (g.step == h->step && g.T == T && g.parity == h->parity && g.ntiles == h->ntiles &&
-            same_exec(g.ex, h->ex)) {
+            g.lmod == h->lidx % 3 && same_exec(g.ex, h->ex)) {
             int rc = h->hip(hipGraphLaunch(g.exec, h->st), "graph launch");
             if (rc) return rc;
             // advance the counters exactly as the captured sequence did
@@ -552,6 +594,7 @@ int run_graph(sim_handle* h, int T) {
                 st += k;
                 t -= k;
                 ++h->launches;
+                ++h->lidx;
             }
             h->step = st;
             h->parity = par;
@@ -562,7 +605,7 @@ int run_graph(sim_handle* h, int T) {
         h->cap = nullptr;
         return SIM_E_STATE;
     }
-    const int step0 = h->step, par0 = h->parity;
+    const int step0 = h->step, par0 = h->parity, lidx0 = h->lidx;
     const unsigned long long l0 = h->launches;
     if (hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return SIM_E_STATE;
@@ -577,13 +620,14 @@ int run_graph(sim_handle* h, int T) {
             (void)hipGraphExecDestroy(h->graphs.front().exec);
             h->graphs.erase(h->graphs.begin());
         }
-        h->graphs.push_back(sim_handle::Graph{step0, T, par0, h->ntiles, h->ex, exec});
+        h->graphs.push_back(sim_handle::Graph{step0, T, par0, h->ntiles, lidx0 % 3, h->ex, exec});
         return h->hip(hipGraphLaunch(exec, h->st), "graph launch");
     }
     if (graph) (void)hipGraphDestroy(graph);
     // capture failed: undo the counter updates, let the caller launch directly
     h->step = step0;
     h->parity = par0;
+    h->lidx = lidx0;
     h->launches = l0;
     h->use_graphs = false;
     return SIM_E_STATE;
@@ -634,8 +678,7 @@ int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best) {
         }
         h->parity = 0;
         h->step = step0;
-        return h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles, 0,
-                                            h->sh), "flags init");
+        return refresh_worklist(h, true);
     };
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return h->fail(SIM_E_HIP, "event create");
@@ -763,8 +806,7 @@ int sim_set_state(sim_handle* h, int32_t s, const uint8_t* in, int32_t step) {
     int rc = h->hip(hipMemsetAsync(h->d_err(), 0, sizeof(int), h->st), "clear error flag");
     if (!rc) rc = h->hip(fs::launch_set_state(h->st, J, in, J.planes[h->parity], h->d_err()),
                          "set state");
-    if (!rc) rc = h->hip(fs::launch_flags_init(h->st, h->d_jobs(), h->d_tile_job(), h->ntiles,
-                                               h->parity, h->sh), "flags init");
+    if (!rc) rc = refresh_worklist(h, true);
     int bad = 0;
     if (!rc) rc = h->hip(hipMemcpyAsync(&bad, h->d_err(), sizeof(int), hipMemcpyDeviceToHost,
                                         h->st), "read error flag");
@@ -872,14 +914,28 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
     rc = h->hip(fs::launch_ckpt_load(h->st, d_adj, njobs, h->max_words), "load checkpoints");
     if (!rc) rc = h->hip(fs::launch_flags_init(h->st, d_adj, d_adj_tiles, h->adj_ntiles, 0,
                                                h->sh), "adjoint flags");
+    auto* amask = reinterpret_cast<unsigned long long*>(h->ws + h->L.adj_masks);
+    const int64_t anw = h->L.adj_mask_words;
+    if (!rc && h->ex.skip)
+        rc = h->hip(fs::launch_mask_init(h->st, d_adj, d_adj_tiles, h->adj_ntiles, 0, amask,
+                                         h->L.adj_mask_words), "adjoint worklist");
+    int alidx = 0;
     if (!rc) rc = h->hip(fs::launch_fill_u32(h->st, reinterpret_cast<uint32_t*>(h->ws + h->L.gpart),
                                              (size_t)h->adj_ntiles * 8, 0u), "zero partials");
     int parity = 0;
     unsigned long long* stats = nullptr;
     for (int off = 0; off < h->ckpt_every && !rc; ) {
         const int k = std::min(h->ex.depth, h->ckpt_every - off);
+        fs::Sched sc{nullptr, nullptr, nullptr, h->L.adj_mask_words};
+        if (h->ex.skip) {
+            sc.in = amask + anw * (alidx % 3);
+            sc.out = amask + anw * ((alidx + 1) % 3);
+            sc.clear = amask + anw * ((alidx + 2) % 3);
+        }
+        ++alidx;
         rc = h->hip(fs::launch_step(h->st, h->sh, true, d_adj, d_adj_tiles, h->adj_ntiles,
-                                    parity, off, k, h->ex.skip, lam, rg, stats), "adjoint kernel");
+                                    parity, off, k, h->ex.skip, lam, rg, sc, h->grid_max, stats),
+                    "adjoint kernel");
         parity ^= 1;
         off += k;
     }

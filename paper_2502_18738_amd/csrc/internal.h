@@ -57,6 +57,17 @@ struct Rings {
     int32_t first, between, last, T;
 };
 
+// Worklist of a launch: bit g of `in` marks global tile g for processing;
+// processed tiles that still hold fire (or changed) mark themselves and their
+// 8 neighbour tiles in `out` for the next launch; `clear` (the mask of the
+// launch after next) is zeroed.  in == nullptr: every tile is launched.
+struct Sched {
+    const unsigned long long* in;
+    unsigned long long* out;
+    unsigned long long* clear;
+    int32_t nwords;
+};
+
 struct TileShape {
     int tr, tc, km;            // rows, words, halo depth (max steps per launch)
 };
@@ -92,7 +103,17 @@ int step_shapes(TileShape* out, int max);
 hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_jobs,
                        const int32_t* d_tile_job, int32_t ntiles, int32_t parity,
                        int32_t t_off, int32_t ksteps, int32_t skip, const float* lam,
-                       Rings rings, unsigned long long* d_stats);
+                       Rings rings, Sched sched, int32_t grid, unsigned long long* d_stats);
+// Worklist for the first launch after a state change: every tile whose 3 x 3
+// tile neighbourhood holds a burning cell (from the flags of `parity`); the
+// three masks (3 * nwords words) are cleared first.
+hipError_t launch_mask_init(hipStream_t st, const DevScen* d_jobs, const int32_t* d_tile_job,
+                            int32_t ntiles, int32_t parity, unsigned long long* masks,
+                            int32_t nwords);
+// Copy every job's planes[parity] into the other buffer (both ping-pong
+// buffers equal, so tiles left out of a worklist stay consistent).
+hipError_t launch_dup_planes(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
+                             int64_t max_words);
 // Copy each job's current planes into checkpoint slot `slot` (forward jobs).
 hipError_t launch_ckpt_save(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
                             int32_t slot, int64_t max_words);

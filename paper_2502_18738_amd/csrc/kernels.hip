@@ -221,7 +221,8 @@ template <int TR, int TC, int KM, bool ADJ, int NT>
 __global__ void __launch_bounds__(NT)
 k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, int32_t ntiles,
        int32_t parity, int32_t t_off, int32_t ksteps, int32_t skip,
-       const float* __restrict__ lam, Rings rings, unsigned long long* __restrict__ stats) {
+       const float* __restrict__ lam, Rings rings, Sched sched,
+       unsigned long long* __restrict__ stats) {
     constexpr int RR = TR + 2 * KM, RC = TC + 2, NW = RR * RC;
     constexpr int WPT = (NW + NT - 1) / NT;
     constexpr int NWAVE = NT / 64;
@@ -236,8 +237,48 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     __shared__ double sG[ADJ ? NWAVE * 4 : 1];
 
     const int tid = threadIdx.x;
-    const int g = xcd_tile(blockIdx.x, gridDim.x);
-    if (g >= ntiles) return;
+
+    // ---- work items: every tile (one per work-group), or the tiles the
+    // previous launch marked (worklist: a fixed grid walks the set bits)
+    __shared__ int sItems, sTile;
+    const bool listed = sched.in != nullptr;
+    int my_pre = 0, my_cnt = 0, my_w0 = 0, my_w1 = 0;
+    if (listed) {
+        const int wpt = (sched.nwords + NT - 1) / NT;
+        my_w0 = min(sched.nwords, tid * wpt);
+        my_w1 = min(sched.nwords, my_w0 + wpt);
+        for (int w = my_w0; w < my_w1; ++w) my_cnt += __popcll(sched.in[w]);
+        int tot;
+        my_pre = block_exscan<NWAVE>(my_cnt, sWave, &tot);
+        if (tid == 0) sItems = tot;
+        for (int w = blockIdx.x * NT + tid; w < sched.nwords; w += gridDim.x * NT)
+            sched.clear[w] = 0ull;
+        __syncthreads();
+    }
+    const int nitems = listed ? sItems : 1;
+    for (int it = listed ? blockIdx.x : 0; it < nitems; it += listed ? gridDim.x : 1) {
+    int g;
+    if (listed) {
+        __syncthreads();   // the previous item's use of LDS is over
+        if (it >= my_pre && it < my_pre + my_cnt) {
+            int k = it - my_pre;
+            for (int w = my_w0; w < my_w1; ++w) {
+                unsigned long long m = sched.in[w];
+                const int c = __popcll(m);
+                if (k < c) {
+                    for (int q = 0; q < k; ++q) m &= m - 1;
+                    sTile = w * 64 + (__ffsll((long long)m) - 1);
+                    break;
+                }
+                k -= c;
+            }
+        }
+        __syncthreads();
+        g = sTile;
+    } else {
+        g = xcd_tile(blockIdx.x, gridDim.x);
+        if (g >= ntiles) continue;
+    }
     const DevScen& J = jobs[tile_job[g]];
     const int lt = g - J.tile0;
     const int trow = lt / J.tiles_c, tcol = lt - trow * J.tiles_c;
@@ -249,7 +290,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     uint32_t* pout = J.planes[parity ^ 1];
 
     const int kj = min(ksteps, J.t_end - (J.t_base + t_off));
-    if (kj <= 0) return;
+    if (kj <= 0) continue;
 
     // ---- skip a tile when no tile within reach holds a burning cell
     bool need = true;
@@ -275,7 +316,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             }
         }
         if (tid == 0) fout[lt] = 2;
-        return;
+        continue;
     }
 
     // ---- load the tile and a KM-row / 1-word halo into LDS
@@ -597,6 +638,19 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         }
         if (tid == 0) atomicAdd(&stats[0], 1ull);
     }
+    if (listed && tid < 9) {
+        // mark the next launch's work: the 3 x 3 tile neighbourhood while the
+        // tile burns, the tile alone when it changed (its two buffers differ)
+        const int f = sFlag;
+        const int dr = tid / 3 - 1, dc = tid - (tid / 3) * 3 - 1;
+        const int rr = trow + dr, cc = tcol + dc;
+        if (((f & 1) || ((f & 2) && tid == 4)) && rr >= 0 && rr < J.tiles_r && cc >= 0 &&
+            cc < J.tiles_c) {
+            const int gn = J.tile0 + rr * J.tiles_c + cc;
+            atomicOr(&sched.out[gn >> 6], 1ull << (gn & 63));
+        }
+    }
+    }  // work items
 }
 
 // ------------------------------------------------- per-edge tables (Eq. 1-5)
@@ -709,8 +763,8 @@ k_prologue(int32_t H, int32_t W, int32_t pitch, const float* __restrict__ p_veg,
 
 __global__ void __launch_bounds__(256)
 k_init_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ ign,
-             uint32_t* __restrict__ planes, float* __restrict__ yhat,
-             int32_t* __restrict__ tign, int32_t* __restrict__ tout) {
+             uint32_t* __restrict__ planes, uint32_t* __restrict__ planes2,
+             float* __restrict__ yhat, int32_t* __restrict__ tign, int32_t* __restrict__ tout) {
     const int r = blockIdx.y;
     const int c = blockIdx.x * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -729,8 +783,8 @@ k_init_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ ig
         const int w = wbase + (lane >> 5);
         if (w < pitch) {
             const int64_t o = (int64_t)r * pitch + w;
-            planes[o] = (uint32_t)(mb >> lane);
-            planes[PW + o] = 0u;
+            planes[o] = planes2[o] = (uint32_t)(mb >> lane);
+            planes[PW + o] = planes2[PW + o] = 0u;
         }
     }
 }
@@ -783,7 +837,7 @@ k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0
 
 __global__ void __launch_bounds__(256)
 k_set_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ in,
-            uint32_t* __restrict__ planes, int* __restrict__ err) {
+            uint32_t* __restrict__ planes, uint32_t* __restrict__ planes2, int* __restrict__ err) {
     const int r = blockIdx.y;
     const int c = blockIdx.x * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -803,8 +857,8 @@ k_set_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ in,
         const int w = wbase + (lane >> 5);
         if (w < pitch) {
             const int64_t o = (int64_t)r * pitch + w;
-            planes[o] = (uint32_t)(mb >> lane);
-            planes[PW + o] = (uint32_t)(md >> lane);
+            planes[o] = planes2[o] = (uint32_t)(mb >> lane);
+            planes[PW + o] = planes2[PW + o] = (uint32_t)(md >> lane);
         }
     }
 }
@@ -1030,7 +1084,36 @@ k_ckpt_load(const DevScen* __restrict__ jobs) {
     const DevScen& J = jobs[blockIdx.y];
     const int64_t nw = 2 * (int64_t)J.H * J.pitch;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nw; i += (int64_t)gridDim.x * 256)
-        J.planes[0][i] = J.ckpt[i];
+        J.planes[0][i] = J.planes[1][i] = J.ckpt[i];
+}
+
+__global__ void __launch_bounds__(256)
+k_dup_planes(const DevScen* __restrict__ jobs, int32_t parity) {
+    const DevScen& J = jobs[blockIdx.y];
+    const int64_t nw = 2 * (int64_t)J.H * J.pitch;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nw; i += (int64_t)gridDim.x * 256)
+        J.planes[parity ^ 1][i] = J.planes[parity][i];
+}
+
+// Worklist of the first launch: tiles with a burning cell in their 3 x 3
+// tile neighbourhood (flags of `parity`).
+__global__ void __launch_bounds__(256)
+k_mask_init(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job,
+            int32_t ntiles, int32_t parity, unsigned long long* __restrict__ mask) {
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= ntiles) return;
+    const DevScen& J = jobs[tile_job[g]];
+    const int lt = g - J.tile0;
+    const int trow = lt / J.tiles_c, tcol = lt - trow * J.tiles_c;
+    bool need = false;
+    for (int dr = -1; dr <= 1; ++dr)
+        for (int dc = -1; dc <= 1; ++dc) {
+            const int rr = trow + dr, cc = tcol + dc;
+            if (rr >= 0 && rr < J.tiles_r && cc >= 0 && cc < J.tiles_c &&
+                (J.flags[parity][rr * J.tiles_c + cc] & 1))
+                need = true;
+        }
+    if (need) atomicOr(&mask[g >> 6], 1ull << (g & 63));
 }
 
 __global__ void k_set_params(DevScen* jobs, ParamBlock pb) {
@@ -1109,8 +1192,27 @@ hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d
 
 hipError_t launch_init_state(hipStream_t st, const DevScen& J, const uint8_t* ign,
                              uint32_t* planes, float* yhat, int32_t* tign, int32_t* tout) {
+    uint32_t* other = planes == J.planes[0] ? J.planes[1] : J.planes[0];
     hipLaunchKernelGGL(k_init_state, cell_grid(J.H, J.pitch * 32), dim3(256), 0, st, J.H, J.W,
-                       J.pitch, ign, planes, yhat, tign, tout);
+                       J.pitch, ign, planes, other, yhat, tign, tout);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_init(hipStream_t st, const DevScen* d_jobs, const int32_t* d_tile_job,
+                            int32_t ntiles, int32_t parity, unsigned long long* masks,
+                            int32_t nwords) {
+    hipError_t e = launch_fill_u32(st, reinterpret_cast<uint32_t*>(masks), (size_t)nwords * 6, 0u);
+    if (e != hipSuccess || ntiles <= 0) return e;
+    hipLaunchKernelGGL(k_mask_init, dim3((ntiles + 255) / 256), dim3(256), 0, st, d_jobs,
+                       d_tile_job, ntiles, parity, masks);
+    return hipGetLastError();
+}
+
+hipError_t launch_dup_planes(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
+                             int64_t max_words) {
+    if (n <= 0) return hipSuccess;
+    const unsigned gx = (unsigned)std::min<int64_t>((2 * max_words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_dup_planes, dim3(gx, n), dim3(256), 0, st, d_jobs, parity);
     return hipGetLastError();
 }
 
@@ -1125,8 +1227,9 @@ hipError_t launch_adjoint_tmap(hipStream_t st, const DevScen* d_jobs, const int3
 
 hipError_t launch_set_state(hipStream_t st, const DevScen& J, const uint8_t* in,
                             uint32_t* planes, int* d_err) {
+    uint32_t* other = planes == J.planes[0] ? J.planes[1] : J.planes[0];
     hipLaunchKernelGGL(k_set_state, cell_grid(J.H, J.pitch * 32), dim3(256), 0, st, J.H, J.W,
-                       J.pitch, in, planes, d_err);
+                       J.pitch, in, planes, other, d_err);
     return hipGetLastError();
 }
 
@@ -1185,7 +1288,7 @@ namespace {
 #endif
 constexpr int kStepThreads = FS_STEP_THREADS;
 using StepFn = void (*)(const DevScen*, const int32_t*, int32_t, int32_t, int32_t, int32_t,
-                        int32_t, const float*, Rings, unsigned long long*);
+                        int32_t, const float*, Rings, Sched, unsigned long long*);
 
 struct StepEntry {
     int tr, tc, km;
@@ -1206,6 +1309,9 @@ const StepEntry kSteps[] = {
     FS_SHAPE(8, 4, 1) FS_SHAPE(8, 4, 4) FS_SHAPE(8, 4, 8)
     FS_SHAPE(8, 8, 1) FS_SHAPE(8, 8, 4) FS_SHAPE(8, 8, 8)
     FS_SHAPE(16, 2, 1) FS_SHAPE(16, 2, 4) FS_SHAPE(16, 2, 8) FS_SHAPE(16, 2, 16)
+    FS_SHAPE(16, 1, 8) FS_SHAPE(16, 1, 16)
+    FS_SHAPE(32, 2, 16) FS_SHAPE(32, 1, 16)
+    FS_SHAPE(8, 2, 8) FS_SHAPE(8, 1, 8)
 };
 #undef FS_SHAPE
 
@@ -1228,12 +1334,13 @@ int step_shapes(TileShape* out, int max) {
 hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_jobs,
                        const int32_t* d_tile_job, int32_t ntiles, int32_t parity,
                        int32_t t_off, int32_t ksteps, int32_t skip, const float* lam,
-                       Rings rings, unsigned long long* d_stats) {
+                       Rings rings, Sched sched, int32_t grid, unsigned long long* d_stats) {
     const StepEntry* e = find_step(sh, adj);
     if (!e) return hipErrorInvalidValue;
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(e->fn, dim3(ntiles), dim3(kStepThreads), 0, st, d_jobs, d_tile_job, ntiles,
-                       parity, t_off, ksteps, skip, lam, rings, d_stats);
+    const int nb = sched.in ? std::max(1, std::min(grid, ntiles)) : ntiles;
+    hipLaunchKernelGGL(e->fn, dim3(nb), dim3(kStepThreads), 0, st, d_jobs, d_tile_job, ntiles,
+                       parity, t_off, ksteps, sched.in ? 0 : skip, lam, rings, sched, d_stats);
     return hipGetLastError();
 }
 
