@@ -14,6 +14,8 @@ Side legs, reported in the same JSON line:
                forward + Eq. 10 BCE loss + adjoint + AdamW, in grad-steps/s;
   batched      256 scenarios with log-uniform sides 256-2048, 300 steps, one
                launch sequence over all of them;
+  paper_sweep  the paper's timing workload shape (square plain map, fixed
+               wind, 300 steps) at sides 50 .. 14000, beside its stated times;
   cpu_baseline the FP64 oracle on the host, on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--legs main,plain,calib,batched,cpu]
@@ -40,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # state, F = (1+p_veg)(1+p_den), elevation, wind speed and direction, and
 # writes 2 bits): 0.5 + 4 + 4 + 8.
 DENSE_BYTES_PER_CELL_STEP = 16.5
-DEFAULT_EXEC = dict(tile_rows=32, tile_words=4, depth=16, skip=True)
+DEFAULT_EXEC = dict(tile_rows=16, tile_words=2, depth=16, skip=True)
 PLAIN_EXEC = dict(tile_rows=16, tile_words=8, depth=1, skip=False)
 
 
@@ -213,7 +215,13 @@ def leg_calib(args, torch, Sim, synth):
                         for b in range(n)])
     del gen
     start = [c[1] for c in cases]
-    sim = Sim(true_s, calib=True, T_max=T, ckpt_every=ck, exec=DEFAULT_EXEC)
+    # the autotuner needs a handle without calibration state: tune a forward
+    # handle over the same scenarios at mid-run, then use its choice
+    tune = Sim(true_s)
+    tune.run(100)
+    cex = tune.autotune(16)
+    del tune
+    sim = Sim(true_s, calib=True, T_max=T, ckpt_every=ck, exec=cex)
     theta = torch.tensor(start, dtype=torch.float32, device="cuda", requires_grad=True)
     opt = torch.optim.AdamW([theta], lr=5e-3)
     pc = torch.tensor([s.p_continue for s in true_s], dtype=torch.float32)
@@ -248,7 +256,7 @@ def leg_calib(args, torch, Sim, synth):
                             "ms_per_grad_step": round(wall_tm / K * 1e3, 2)},
         "config": {"workload": "64 scenarios 1024x1024, 200 steps, checkpoints every 20, "
                                "BCE loss, AdamW lr 5e-3 with clamps",
-                   "exec": DEFAULT_EXEC},
+                   "exec": cex},
     }
 
 
@@ -275,6 +283,42 @@ def leg_batched(args, torch, Sim, synth):
     }
 
 
+# The paper's stated timings for 300 steps on a square plain map (Sec. 3,
+# forward prediction; the figure itself is not available): side -> seconds,
+# device.  "<" marks an upper bound stated in the text.
+PAPER_300 = {
+    800: ("0.52 s (flat for every side <= 800)", "RTX 4090"),
+    1200: ("< 1 s", "RTX 4090"),
+    1500: ("< 1 s", "A800"),
+    8000: ("largest side that fits", "RTX 4090"),
+    14000: ("< 60 s", "'a more advanced GPU'"),
+}
+
+
+def leg_paper_sweep(args, torch, Sim, synth):
+    """Sides 50 .. 14000 of the paper's 300-step plain-map workload."""
+    out = []
+    for side in (50, 200, 800, 1200, 1500, 4000, 8000, 14000):
+        s = synth.paper_plain(side)
+        sim = Sim([s], exec=DEFAULT_EXEC)
+
+        def run():
+            sim.reset()
+            sim.run(300)
+
+        wall, gpu = timed(run, 2, 1, torch)
+        row = {"side": side, "ms_per_300_steps": round(wall / 2 * 1e3, 3),
+               "G_cell_steps_per_s": round(side * side * 300 * 2 / wall / 1e9, 3)}
+        if side in PAPER_300:
+            row["paper"] = {"time": PAPER_300[side][0], "device": PAPER_300[side][1]}
+        out.append(row)
+        log("paper sweep", row)
+        del sim
+        torch.cuda.empty_cache()
+    return {"workload": "square plain map (flat, neutral fuel), uniform wind 5 m/s toward "
+                        "45 deg, centre ignition, 300 steps", "rows": out}
+
+
 def leg_cpu(args, s):
     import oracle
     steps = 40
@@ -292,7 +336,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--legs", default="main,plain,calib,batched,cpu")
+    ap.add_argument("--legs", default="main,plain,calib,batched,paper,cpu")
     ap.add_argument("--exec", default=None, metavar="TR,TC,DEPTH,SKIP",
                     help="execution shape of the main leg (tile rows, tile words, steps "
                          "per launch, skip 0/1)")
@@ -353,6 +397,8 @@ def main():
         res["calibration"] = leg_calib(args, torch, Sim, synth)
     if "batched" in legs:
         res["batched"] = leg_batched(args, torch, Sim, synth)
+    if "paper" in legs:
+        res["paper_sweep"] = leg_paper_sweep(args, torch, Sim, synth)
     if "cpu" in legs:
         log("cpu baseline")
         res["cpu_baseline"] = leg_cpu(args, s2)

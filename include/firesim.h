@@ -106,8 +106,11 @@ typedef struct {
 } sim_desc;
 
 /* Execution shape: rows x words of one tile (a word is 32 cells), steps per
- * launch (temporal block depth, 1 <= depth <= tile_rows and <= 32), and
- * whether tiles with no burning cell within reach are skipped.  Every shape
+ * launch (temporal block depth, 1 <= depth <= tile_rows and <= 16), and how
+ * tiles with no burning cell within reach are skipped: 0 = every tile is
+ * processed, 1 = a device-built worklist (tiles that burn mark their
+ * neighbours for the next launch; a grid of resident work-groups walks it),
+ * 2 = every tile is launched and tests its neighbours' flags.  Every shape
  * produces bit-identical states. */
 typedef struct {
     int32_t tile_rows, tile_words, depth, skip;
@@ -130,7 +133,7 @@ SIM_API int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* w
              size_t ws_bytes, void* stream, uint32_t flags, int32_t ckpt_every,
              int32_t T_max);
 
-/* Choose the execution shape (default: 16 rows x 4 words, depth 16, skip on;
+/* Choose the execution shape (default: 16 rows x 2 words, depth 16, worklist skipping;
  * sim_autotune picks one by timing).  Only whitelisted shapes are compiled; others give
  * SIM_E_SHAPE. */
 SIM_API int sim_set_exec(sim_handle* h, const sim_exec* e);

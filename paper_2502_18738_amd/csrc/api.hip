@@ -398,12 +398,13 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
         if (hipGetDevice(&dev) == hipSuccess &&
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
             cus > 0)
-            h->grid_max = 4 * cus;
+            h->grid_max = 64 * cus;   // upper bound; occupancy decides the launch size
     }
     // default execution shape
     int32_t max_pitch = 0;
     for (const auto& s : h->L.s) max_pitch = std::max(max_pitch, s.pitch);
-    h->ex = sim_exec{16, max_pitch <= 2 ? 2 : 4, 16, 1};
+    h->ex = sim_exec{16, 2, 16, 1};
+    (void)max_pitch;
     h->sh = shape_of(h->ex);
 
     h->job.resize(n);
@@ -508,8 +509,8 @@ int sim_set_exec(sim_handle* h, const sim_exec* e) {
         (h->calib() && !fs::step_shape_supported(sh, true)))
         return h->fail(SIM_E_SHAPE, "tile %dx%d words with depth %d is not compiled in",
                        e->tile_rows, e->tile_words, e->depth);
+    if (e->skip < 0 || e->skip > 2) return h->fail(SIM_E_ARG, "skip must be 0, 1 or 2");
     h->ex = *e;
-    h->ex.skip = e->skip ? 1 : 0;
     const bool same = sh.tr == h->sh.tr && sh.tc == h->sh.tc;
     h->sh = sh;
     if (same) return refresh_worklist(h, true);
@@ -532,7 +533,7 @@ int enqueue_run(sim_handle* h, hipStream_t st, int T, unsigned long long* stats)
         int k = std::min(h->ex.depth, T);
         if (h->calib()) k = std::min(k, h->ckpt_every - h->step % h->ckpt_every);
         fs::Sched sc{nullptr, nullptr, nullptr, h->L.mask_words};
-        if (h->ex.skip) {
+        if (h->ex.skip == 1) {
             unsigned long long* m = h->d_masks();
             const int64_t nw = h->L.mask_words;
             sc.in = m + nw * (h->lidx % 3);
@@ -690,8 +691,8 @@ int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best) {
     h->use_graphs = false;
     float best_ms = 1e30f;
     sim_exec best_ex = ex0;
-    for (int c = 0; c < ns && !rc; ++c) {
-        const sim_exec ex{shapes[c].tr, shapes[c].tc, shapes[c].km, 1};
+    for (int c = 0; c < 2 * ns && !rc; ++c) {
+        const sim_exec ex{shapes[c % ns].tr, shapes[c % ns].tc, shapes[c % ns].km, 1 + c / ns};
         rc = sim_set_exec(h, &ex);
         if (!rc) rc = restore();
         if (!rc) rc = enqueue_run(h, h->st, T_probe, nullptr);   // warm-up
@@ -916,7 +917,7 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
                                                h->sh), "adjoint flags");
     auto* amask = reinterpret_cast<unsigned long long*>(h->ws + h->L.adj_masks);
     const int64_t anw = h->L.adj_mask_words;
-    if (!rc && h->ex.skip)
+    if (!rc && h->ex.skip == 1)
         rc = h->hip(fs::launch_mask_init(h->st, d_adj, d_adj_tiles, h->adj_ntiles, 0, amask,
                                          h->L.adj_mask_words), "adjoint worklist");
     int alidx = 0;
@@ -927,7 +928,7 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
     for (int off = 0; off < h->ckpt_every && !rc; ) {
         const int k = std::min(h->ex.depth, h->ckpt_every - off);
         fs::Sched sc{nullptr, nullptr, nullptr, h->L.adj_mask_words};
-        if (h->ex.skip) {
+        if (h->ex.skip == 1) {
             sc.in = amask + anw * (alidx % 3);
             sc.out = amask + anw * ((alidx + 1) % 3);
             sc.clear = amask + anw * ((alidx + 2) % 3);

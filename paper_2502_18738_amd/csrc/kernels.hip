@@ -1294,13 +1294,14 @@ struct StepEntry {
     int tr, tc, km;
     bool adj;
     StepFn fn;
+    int resident;   // work-groups resident at once on the device (0: not queried yet)
 };
 
-#define FS_SHAPE(TR, TC, KM)                                   \
-    {TR, TC, KM, false, &k_step<TR, TC, KM, false, kStepThreads>}, \
-    {TR, TC, KM, true, &k_step<TR, TC, KM, true, kStepThreads>},
+#define FS_SHAPE(TR, TC, KM)                                      \
+    {TR, TC, KM, false, &k_step<TR, TC, KM, false, kStepThreads>, 0}, \
+    {TR, TC, KM, true, &k_step<TR, TC, KM, true, kStepThreads>, 0},
 
-const StepEntry kSteps[] = {
+StepEntry kSteps[] = {
     FS_SHAPE(16, 4, 1) FS_SHAPE(16, 4, 4) FS_SHAPE(16, 4, 8) FS_SHAPE(16, 4, 16)
     FS_SHAPE(16, 8, 1) FS_SHAPE(16, 8, 4) FS_SHAPE(16, 8, 8) FS_SHAPE(16, 8, 16)
     FS_SHAPE(32, 4, 1) FS_SHAPE(32, 4, 8) FS_SHAPE(32, 4, 16)
@@ -1338,7 +1339,23 @@ hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_
     const StepEntry* e = find_step(sh, adj);
     if (!e) return hipErrorInvalidValue;
     if (ntiles <= 0) return hipSuccess;
-    const int nb = sched.in ? std::max(1, std::min(grid, ntiles)) : ntiles;
+    int nb = ntiles;
+    if (sched.in) {
+        // as many work-groups as can be resident at once (occupancy x CUs),
+        // capped by the caller and by the tile count
+        if (e->resident == 0) {
+            int per_cu = 0, dev = 0, cus = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->fn, kStepThreads, 0) !=
+                    hipSuccess || per_cu < 1)
+                per_cu = 4;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                    hipSuccess || cus < 1)
+                cus = 256;
+            const_cast<StepEntry*>(e)->resident = per_cu * cus;
+        }
+        nb = std::max(1, std::min(std::min(grid, e->resident), ntiles));
+    }
     hipLaunchKernelGGL(e->fn, dim3(nb), dim3(kStepThreads), 0, st, d_jobs, d_tile_job, ntiles,
                        parity, t_off, ksteps, sched.in ? 0 : skip, lam, rings, sched, d_stats);
     return hipGetLastError();

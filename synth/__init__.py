@@ -18,6 +18,7 @@ from .fields import (  # noqa: F401
     config2,
     config3_scenario,
     config3_sizes,
+    paper_plain,
     config4_scenario,
     synthetic_front_state,
     encode_planes,

@@ -191,6 +191,21 @@ def config2(seed=2, size=4096, T=1000):
                       ignition_patch=(r0, r0, n), T=T)
 
 
+def paper_plain(side, T=300, wind_speed=5.0, wind_dir=45.0):
+    """The paper's timing workload shape (Sec. 3, forward prediction): a square
+    plain landscape (flat, uniform neutral fuel) with fixed wind and a centre
+    ignition, 300 steps."""
+    z = np.zeros((side, side), dtype=np.float32)
+    ign = np.zeros((side, side), dtype=np.uint8)
+    ign[side // 2, side // 2] = 1
+    s = Scenario(H=side, W=side, p_veg=z, p_den=z.copy(), elevation=z.copy(),
+                 wind_speed=None, wind_dir=None,
+                 wind_speed_scalar=float(np.float32(wind_speed)),
+                 wind_dir_scalar=float(np.float32(wind_dir)),
+                 init_burning=ign, seed=side, T=T)
+    return s.with_params(*s.params)
+
+
 def config3_sizes(n=256):
     """Grid sides (H_b, W_b) of the batched ensemble, log-uniform in [256, 2048]."""
     out = []
