@@ -80,8 +80,9 @@ typedef struct {
  * row-major, caller-owned.  p_veg = -1 (or p_den = -1) marks a cell without
  * fuel (Sec. 2.2: a small enough p_veg gives zero propagation); values below
  * -1 are rejected.  Slope is derived from the elevation with Eq. 1 in place of
- * the paper's H x W x 3 x 3 slope tensor.  wind_speed / wind_dir_deg may be
- * NULL, in which case the two scalars apply to every cell. */
+ * the paper's H x W x 3 x 3 slope tensor unless slope_deg is given.
+ * wind_speed / wind_dir_deg may be NULL, in which case the two scalars apply
+ * to every cell. */
 typedef struct {
     const float* p_veg;
     const float* p_den;
@@ -91,6 +92,11 @@ typedef struct {
     float wind_speed_scalar;
     float wind_dir_deg_scalar;
     const uint8_t* init_burning;   /* H*W bytes, non-zero = burning at t = 0 */
+    /* Optional: the paper's slope tensor (Sec. 2.1), H*W*3*3 FP32 degrees;
+     * element [r][c][dr+1][dc+1] is theta_s of Eq. 4 for the edge from
+     * neighbour (r+dr, c+dc) into (r, c), positive when the spread runs
+     * uphill.  When non-NULL it replaces Eq. 1 and elevation_m may be NULL. */
+    const float* slope_deg;
 } sim_fields;
 
 /* One scenario.  cell_m is l of Eq. 1 in metres; seed keys the Philox stream;
@@ -216,6 +222,31 @@ SIM_API int sim_set_adjoint(sim_handle* h, int32_t method, int32_t r_first, int3
  * FP64 n, grad device FP64 n x 4 (p_h, a, c1, c2).  Calibration mode only. */
 SIM_API int sim_loss_grad(sim_handle* h, const uint8_t* target, int32_t loss_kind, double* loss,
                   double* grad);
+
+/* Replace scenario s's wind (Algorithm 1 updates the wind per observation):
+ * device FP32 H*W fields or NULL for the scalars, as in sim_fields.  Takes
+ * effect from the next step.  In calibration mode only at step 0 (right
+ * after sim_reset), so that a run and its adjoint see one wind.  Validates on
+ * the device and waits for the stream; the fields are read during the call
+ * only (unlike sim_fields, they need not outlive it). */
+SIM_API int sim_set_wind(sim_handle* h, int32_t s, const float* wind_speed,
+                         const float* wind_dir_deg, float wind_speed_scalar,
+                         float wind_dir_deg_scalar);
+
+/* Spotting (Sec. 2.2): set `count` cells of scenario s burning in place, as
+ * extra ignition points, before the next step.  `cells` is a device int32
+ * array of r*W + c indices; indices outside the grid and cells already
+ * burned are ignored.  Not available in calibration mode. */
+SIM_API int sim_ignite(sim_handle* h, int32_t s, const int32_t* cells, int32_t count);
+
+/* Burning and burned cell counts of every scenario (device int64, n x 2):
+ * the affected-cell counts of Eq. 12. */
+SIM_API int sim_counts(sim_handle* h, int64_t* out);
+
+/* Overlap of scenario s's affected cells (burning or burned) with `target`
+ * (device uint8 H*W, non-zero = affected): out (device int64 x 2) =
+ * (|A intersect B|, |A union B|); Eq. 11's Jaccard index is their ratio. */
+SIM_API int sim_overlap(sim_handle* h, int32_t s, const uint8_t* target, int64_t* out);
 
 /* Counters accumulated since the last reset with SIM_F_STATS (host array of
  * 4): processed tiles, ignition + continue trials, ignition trials with

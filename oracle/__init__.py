@@ -52,6 +52,7 @@ class _Problem(ctypes.Structure):
         ("p_veg", ctypes.c_void_p), ("p_den", ctypes.c_void_p), ("elev", ctypes.c_void_p),
         ("wind_speed", ctypes.c_void_p), ("wind_dir", ctypes.c_void_p),
         ("wind_speed_scalar", ctypes.c_double), ("wind_dir_scalar", ctypes.c_double),
+        ("slope9", ctypes.c_void_p),
     ]
 
 
@@ -80,6 +81,7 @@ def _load():
     lib.fo_loss.argtypes = [i32, i32, vp, vp, i32, vp]
     lib.fo_loss.restype = dbl
     lib.fo_grad.argtypes = [P, i32, vp, vp, vp]
+    lib.fo_slope_tensor.argtypes = [P, vp]
     _lib = lib
     return lib
 
@@ -97,6 +99,7 @@ class Problem:
         self.p_veg, self.p_den = f(scn.p_veg), f(scn.p_den)
         self.elev = f(scn.elevation)
         self.ws, self.wd = f(scn.wind_speed), f(scn.wind_dir)
+        self.slope9 = f(getattr(scn, "slope_deg", None))
         par = {k: float(np.float32(getattr(scn, k)))
                for k in ("p_h", "a", "c1", "c2", "p_continue")}
         par.update({k: float(v) for k, v in override.items()
@@ -109,7 +112,7 @@ class Problem:
                           float(c), _ptr(self.p_veg), _ptr(self.p_den), _ptr(self.elev),
                           _ptr(self.ws), _ptr(self.wd),
                           float(np.float32(scn.wind_speed_scalar)),
-                          float(np.float32(scn.wind_dir_scalar)))
+                          float(np.float32(scn.wind_dir_scalar)), _ptr(self.slope9))
         self.init_burning = np.ascontiguousarray(scn.init_burning, dtype=np.uint8)
 
     @property
@@ -145,6 +148,32 @@ def edge_q(scn, r, c, dr, dc, **kw):
     th, cd = ctypes.c_double(), ctypes.c_double()
     q = lib.fo_edge_q(pb.ref, r, c, dr, dc, ctypes.byref(th), ctypes.byref(cd))
     return q, th.value, cd.value
+
+
+def slope_tensor(scn):
+    """Eq. 1 in the paper's H x W x 3 x 3 layout (degrees, FP32)."""
+    lib = _load()
+    pb = _problem(scn)
+    out = np.zeros((pb.H, pb.W, 3, 3), dtype=np.float32)
+    lib.fo_slope_tensor(pb.ref, out.ctypes.data)
+    return out
+
+
+def affected(S):
+    """Burning or burned cells of a state (the affected area of Eq. 11-12)."""
+    return np.asarray(S) != 0
+
+
+def jaccard(A, B):
+    """Eq. 11: |A intersect B| / |A union B| of two affected-area masks."""
+    A, B = np.asarray(A, bool), np.asarray(B, bool)
+    u = np.count_nonzero(A | B)
+    return 1.0 if u == 0 else np.count_nonzero(A & B) / u
+
+
+def manhattan(counts_a, counts_b):
+    """Eq. 12: sum over time of |A_t - B_t| of affected-cell counts."""
+    return float(np.sum(np.abs(np.asarray(counts_a, float) - np.asarray(counts_b, float))))
 
 
 def initial_state(scn):

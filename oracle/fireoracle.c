@@ -105,11 +105,16 @@ static void edge_eval(const fo_problem* pb, int32_t r, int32_t c, int32_t dr, in
     const int64_t j = (int64_t)r * W + c;
     const int64_t i = (int64_t)(r + dr) * W + (c + dc);
 
-    /* Eq. 1: slope between the receiving cell j and the burning neighbour i. */
-    double k = (dr != 0 && dc != 0) ? sqrt(2.0) : 1.0;
-    double Ej = (double)pb->elev[j];
-    double Ei = (double)pb->elev[i];
-    e->theta_s = atan((Ej - Ei) / (k * pb->cell_m)) * (180.0 / M_PI);
+    /* Eq. 1: slope between the receiving cell j and the burning neighbour i
+     * (or the given slope tensor, the paper's own input form). */
+    if (pb->slope9) {
+        e->theta_s = (double)pb->slope9[j * 9 + (dr + 1) * 3 + (dc + 1)];
+    } else {
+        double k = (dr != 0 && dc != 0) ? sqrt(2.0) : 1.0;
+        double Ej = (double)pb->elev[j];
+        double Ei = (double)pb->elev[i];
+        e->theta_s = atan((Ej - Ei) / (k * pb->cell_m)) * (180.0 / M_PI);
+    }
 
     /* Eq. 3: theta_w is the angle between the wind heading and the spread
      * direction i -> j. */
@@ -138,6 +143,24 @@ double fo_edge_q(const fo_problem* pb, int32_t r, int32_t c, int32_t dr, int32_t
     if (theta_s_out) *theta_s_out = e.theta_s;
     if (cosd_out) *cosd_out = e.cosd;
     return e.q;
+}
+
+void fo_slope_tensor(const fo_problem* pb, float* out9)
+{
+    for (int32_t r = 0; r < pb->H; ++r)
+        for (int32_t c = 0; c < pb->W; ++c)
+            for (int32_t dr = -1; dr <= 1; ++dr)
+                for (int32_t dc = -1; dc <= 1; ++dc) {
+                    int64_t j = (int64_t)r * pb->W + c;
+                    double v = 0.0;
+                    int rr = r + dr, cc = c + dc;
+                    if ((dr || dc) && rr >= 0 && rr < pb->H && cc >= 0 && cc < pb->W) {
+                        double k = (dr != 0 && dc != 0) ? sqrt(2.0) : 1.0;
+                        double Ei = (double)pb->elev[(int64_t)rr * pb->W + cc];
+                        v = atan(((double)pb->elev[j] - Ei) / (k * pb->cell_m)) * (180.0 / M_PI);
+                    }
+                    out9[j * 9 + (dr + 1) * 3 + (dc + 1)] = (float)v;
+                }
 }
 
 static int burning_at(const fo_problem* pb, const uint8_t* S, int32_t r, int32_t c)

@@ -53,6 +53,7 @@ typedef struct {
     const float *p_veg, *p_den, *elev;       /* H*W */
     const float *wind_speed, *wind_dir;      /* H*W, or NULL -> scalars */
     double wind_speed_scalar, wind_dir_scalar;
+    const float *slope9;           /* H*W*3*3 degrees (paper layout) or NULL -> Eq. 1 */
 } fo_problem;
 
 /* Philox4x32-10 (Salmon et al., SC'11): 10 rounds of the 4x32 S-box. */

@@ -15,14 +15,14 @@ from ._abi import (  # noqa: F401
     load,
 )
 
-__all__ = ["load", "Sim", "SimError", "FireCalib", "calibrate"]
+__all__ = ["load", "Sim", "SimError", "FireCalib", "calibrate", "calibrate_sequence"]
 
 
 def __getattr__(name):
     if name == "Sim":
         from .sim import Sim
         return Sim
-    if name in ("FireCalib", "calibrate"):
+    if name in ("FireCalib", "calibrate", "calibrate_sequence"):
         from . import calib
         return getattr(calib, name)
     raise AttributeError(name)

@@ -45,7 +45,8 @@ class sim_fields(ctypes.Structure):
     _fields_ = [("p_veg", ctypes.c_void_p), ("p_den", ctypes.c_void_p),
                 ("elevation_m", ctypes.c_void_p), ("wind_speed", ctypes.c_void_p),
                 ("wind_dir_deg", ctypes.c_void_p), ("wind_speed_scalar", ctypes.c_float),
-                ("wind_dir_deg_scalar", ctypes.c_float), ("init_burning", ctypes.c_void_p)]
+                ("wind_dir_deg_scalar", ctypes.c_float), ("init_burning", ctypes.c_void_p),
+                ("slope_deg", ctypes.c_void_p)]
 
 
 class sim_desc(ctypes.Structure):
@@ -64,7 +65,7 @@ EXPORTS = (
     "sim_get_step", "sim_set_params", "sim_reset", "sim_get_state", "sim_set_state",
     "sim_pignite", "sim_accumulator", "sim_adjoint", "sim_loss_grad", "sim_stats",
     "sim_last_error", "sim_destroy", "sim_version", "sim_autotune", "sim_use_graphs",
-    "sim_set_adjoint",
+    "sim_set_adjoint", "sim_set_wind", "sim_ignite", "sim_counts", "sim_overlap",
 )
 
 _lib = None
@@ -109,6 +110,10 @@ def load():
         "sim_autotune": (ctypes.c_int, [H, i32, ctypes.POINTER(sim_exec)]),
         "sim_use_graphs": (ctypes.c_int, [H, i32]),
         "sim_set_adjoint": (ctypes.c_int, [H, i32, i32, i32, i32]),
+        "sim_set_wind": (ctypes.c_int, [H, i32, vp, vp, ctypes.c_float, ctypes.c_float]),
+        "sim_ignite": (ctypes.c_int, [H, i32, vp, i32]),
+        "sim_counts": (ctypes.c_int, [H, vp]),
+        "sim_overlap": (ctypes.c_int, [H, i32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

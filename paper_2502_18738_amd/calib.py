@@ -90,3 +90,41 @@ def calibrate(sim: Sim, target, theta0, *, T: int, steps: int = 50, lr: float = 
         if callback is not None:
             callback(g, loss, theta)
     return theta.detach(), history
+
+
+def calibrate_sequence(sim: Sim, observations, theta0, *, interval: int, epochs: int = 1,
+                       lr: float = 5e-3, loss_kind: int = SIM_LOSS_BCE, winds=None,
+                       seed0: int = 1000):
+    """Algorithm 1 with several observations per epoch.
+
+    ``observations[it]`` (uint8, the n grids concatenated) is the observed
+    fire after (it + 1) * interval steps; ``winds[it]`` (optional) is a list of
+    (speed field or None, direction field or None, speed scalar, direction
+    scalar) per scenario, set before the replay of iteration it.  Each epoch
+    draws a new seed and keeps it for all of its iterations (Sec. 2.3); every
+    iteration replays the fire from the start with the latest parameters,
+    takes the Eq. 10 loss and its gradient, one AdamW step and the clamps.
+    Returns (theta, history of (epoch, iteration, loss per scenario, theta)).
+    """
+    theta = torch.as_tensor(theta0, dtype=torch.float32, device=sim.device).clone()
+    theta.requires_grad_(True)
+    opt = torch.optim.AdamW([theta], lr=lr)
+    history = []
+    for ep in range(epochs):
+        seed = seed0 + ep
+        for it, obs in enumerate(observations):
+            p = theta.detach().to("cpu")
+            sim.set_params([tuple(r) + (pc,) for r, pc in zip(p.tolist(), sim.p_continue)])
+            sim.reset([seed] * sim.n)
+            if winds is not None:
+                for s_, w in enumerate(winds[it]):
+                    sim.set_wind(s_, *w)
+            sim.run((it + 1) * int(interval))
+            y = torch.as_tensor(obs, device=sim.device).to(torch.uint8).view(-1)
+            loss, grad = sim.loss_grad(y, loss_kind)
+            theta.grad = grad.to(theta.dtype)
+            opt.step()
+            opt.zero_grad(set_to_none=True)
+            clamp_(theta)
+            history.append((ep, it, loss.detach().cpu(), theta.detach().cpu().clone()))
+    return theta.detach(), history

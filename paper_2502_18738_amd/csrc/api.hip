@@ -163,7 +163,7 @@ int check_descs(const sim_desc* d, int n, std::string* why) {
             return SIM_E_PARAM;
         }
         const sim_fields& f = d[i].f;
-        if (!f.p_veg || !f.p_den || !f.elevation_m || !f.init_burning) {
+        if (!f.p_veg || !f.p_den || !(f.elevation_m || f.slope_deg) || !f.init_burning) {
             snprintf(buf, sizeof buf, "scenario %d: a required field pointer is NULL", i);
             *why = buf;
             return SIM_E_ARG;
@@ -179,7 +179,7 @@ int check_descs(const sim_desc* d, int n, std::string* why) {
             return SIM_E_PARAM;
         }
         if (((uintptr_t)f.p_veg | (uintptr_t)f.p_den | (uintptr_t)f.elevation_m |
-             (uintptr_t)f.wind_speed | (uintptr_t)f.wind_dir_deg) & 3u) {
+             (uintptr_t)f.wind_speed | (uintptr_t)f.wind_dir_deg | (uintptr_t)f.slope_deg) & 3u) {
             snprintf(buf, sizeof buf, "scenario %d: FP32 fields must be 4-byte aligned", i);
             *why = buf;
             return SIM_E_ARG;
@@ -459,8 +459,8 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
                     "prologue");
     }
     for (int i = 0; i < n && !rc; ++i)
-        rc = h->hip(fs::launch_slopes(h->st, h->job[i], const_cast<float*>(h->job[i].th8)),
-                    "slope table");
+        rc = h->hip(fs::launch_slopes(h->st, h->job[i], const_cast<float*>(h->job[i].th8),
+                                      descs[i].f.slope_deg, h->d_err()), "slope table");
     h->cell0.assign(1, 0);
     for (int i = 0; i < n; ++i) h->cell0.push_back(h->cell0.back() + (int64_t)descs[i].H * descs[i].W);
     for (int i = 0; i < n; ++i) h->job[i].lam_off = h->cell0[i];
@@ -487,6 +487,7 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
         if (bad & 4) m += " non-finite elevation;";
         if (bad & 8) m += " wind speed < 0 or non-finite;";
         if (bad & 16) m += " non-finite wind direction;";
+        if (bad & 64) m += " non-finite slope_deg entry;";
         g_init_error = m;
         delete h;
         return SIM_E_PARAM;
@@ -986,6 +987,65 @@ int sim_loss_grad(sim_handle* h, const uint8_t* target, int32_t kind, double* lo
         off += (int64_t)J.H * J.W;
     }
     return adjoint(h, lam, grad);
+}
+
+int sim_set_wind(sim_handle* h, int32_t s, const float* wind_speed, const float* wind_dir_deg,
+                 float wind_speed_scalar, float wind_dir_deg_scalar) {
+    if (!h) return SIM_E_ARG;
+    if (s < 0 || s >= h->n) return h->fail(SIM_E_ARG, "scenario index %d out of range", s);
+    if (((uintptr_t)wind_speed | (uintptr_t)wind_dir_deg) & 3u)
+        return h->fail(SIM_E_ARG, "wind fields must be 4-byte aligned");
+    if (!wind_speed && (!std::isfinite(wind_speed_scalar) || wind_speed_scalar < 0.f))
+        return h->fail(SIM_E_PARAM, "wind_speed_scalar must be finite, >= 0");
+    if (!wind_dir_deg && !std::isfinite(wind_dir_deg_scalar))
+        return h->fail(SIM_E_PARAM, "wind_dir_deg_scalar must be finite");
+    if (h->calib() && h->step != 0)
+        return h->fail(SIM_E_STATE, "in calibration mode the wind may change only at step 0");
+    const fs::DevScen& J = h->job[s];
+    int rc = h->hip(hipMemsetAsync(h->d_err(), 0, sizeof(int), h->st), "clear error flag");
+    if (!rc) rc = h->hip(fs::launch_set_wind(h->st, J, wind_speed, wind_dir_deg, wind_speed_scalar,
+                                             wind_dir_deg_scalar, const_cast<float4*>(J.rec),
+                                             h->d_err()), "set wind");
+    int bad = 0;
+    if (!rc) rc = h->hip(hipMemcpyAsync(&bad, h->d_err(), sizeof(int), hipMemcpyDeviceToHost,
+                                        h->st), "read error flag");
+    if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (rc) return rc;
+    h->q_dirty = true;
+    h->d[s].f.wind_speed = wind_speed;
+    h->d[s].f.wind_dir_deg = wind_dir_deg;
+    h->d[s].f.wind_speed_scalar = wind_speed_scalar;
+    h->d[s].f.wind_dir_deg_scalar = wind_dir_deg_scalar;
+    if (bad) return h->fail(SIM_E_PARAM, "wind speed < 0 or non-finite wind (the record was "
+                            "written; set a valid wind before running)");
+    return SIM_OK;
+}
+
+int sim_ignite(sim_handle* h, int32_t s, const int32_t* cells, int32_t count) {
+    if (!h) return SIM_E_ARG;
+    if (s < 0 || s >= h->n) return h->fail(SIM_E_ARG, "scenario index %d out of range", s);
+    if (count < 0) return h->fail(SIM_E_SHAPE, "count must be >= 0");
+    if (count > 0 && !cells) return h->fail(SIM_E_ARG, "cells is NULL");
+    if (h->calib()) return h->fail(SIM_E_STATE, "sim_ignite is not available in calibration mode");
+    if (count == 0) return SIM_OK;
+    int rc = h->hip(fs::launch_ignite(h->st, h->job[s], cells, count), "ignite");
+    if (!rc) rc = refresh_worklist(h, false);   // both buffers were written
+    return rc;
+}
+
+int sim_counts(sim_handle* h, int64_t* out) {
+    if (!h) return SIM_E_ARG;
+    if (!out) return h->fail(SIM_E_ARG, "out is NULL");
+    return h->hip(fs::launch_counts(h->st, h->d_jobs(), h->n, h->parity, h->max_words,
+                                    reinterpret_cast<long long*>(out)), "counts");
+}
+
+int sim_overlap(sim_handle* h, int32_t s, const uint8_t* target, int64_t* out) {
+    if (!h) return SIM_E_ARG;
+    if (s < 0 || s >= h->n) return h->fail(SIM_E_ARG, "scenario index %d out of range", s);
+    if (!target || !out) return h->fail(SIM_E_ARG, "target and out must be non-NULL");
+    return h->hip(fs::launch_overlap(h->st, h->job[s], h->parity, target,
+                                     reinterpret_cast<long long*>(out)), "overlap");
 }
 
 int sim_stats(sim_handle* h, uint64_t out[4]) {

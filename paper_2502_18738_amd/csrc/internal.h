@@ -78,8 +78,22 @@ hipError_t launch_prologue(hipStream_t st, const DevScen* d_job, const DevScen& 
                            const float* p_veg, const float* p_den, const float* ws,
                            const float* wd, float ws0, float wd0, const uint8_t* ign,
                            float4* rec, uint32_t* fuel, float* yhat, int* d_err);
-// Slope table th8 of one scenario from its elevation (after the prologue).
-hipError_t launch_slopes(hipStream_t st, const DevScen& job, float* th8);
+// Slope table th8 of one scenario from its elevation (after the prologue),
+// or from the paper-layout H x W x 3 x 3 slope tensor when slope9 != nullptr
+// (non-finite entries set bit 64 of *d_err).
+hipError_t launch_slopes(hipStream_t st, const DevScen& job, float* th8, const float* slope9,
+                         int* d_err);
+// Wind of one scenario: rewrite (V, V cos, V sin) of rec (F kept).
+hipError_t launch_set_wind(hipStream_t st, const DevScen& job, const float* ws, const float* wd,
+                           float ws0, float wd0, float4* rec, int* d_err);
+// Set listed cells burning in both ping-pong buffers (spotting).
+hipError_t launch_ignite(hipStream_t st, const DevScen& job, const int32_t* cells, int32_t count);
+// out[2s], out[2s+1] += burning / burned counts of every job (out zeroed first).
+hipError_t launch_counts(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
+                         int64_t max_words, long long* out);
+// out = (|A & B|, |A | B|) for affected cells A of one job and target B.
+hipError_t launch_overlap(hipStream_t st, const DevScen& job, int32_t parity, const uint8_t* target,
+                          long long* out);
 // Propagation table q8 of every scenario for the current parameters.
 // d_cell0: n + 1 prefix sums of cell counts (block ranges per scenario).
 hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,

@@ -656,23 +656,37 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
 // ------------------------------------------------- per-edge tables (Eq. 1-5)
 
 // th8[j][m] = Eq. 1 slope from neighbour slot m up to cell j (0 where the
-// neighbour is outside the grid; such slots never burn).
+// neighbour is outside the grid; such slots never burn), or the matching
+// entry of the paper-layout slope tensor slope9[j][dr+1][dc+1].
 __global__ void __launch_bounds__(256)
-k_slopes(DevScen J, float* __restrict__ th8) {
+k_slopes(DevScen J, float* __restrict__ th8, const float* __restrict__ slope9,
+         int* __restrict__ err) {
     const int r = blockIdx.y;
     const int c = blockIdx.x * 256 + threadIdx.x;
     if (c >= J.W) return;
     const int64_t j = (int64_t)r * J.W + c;
-    const float Ej = J.elev[j];
     float th[8];
+    if (slope9) {
+        bool bad = false;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        int dr, dc;
-        slot_dir(m, dr, dc);
-        const int rr = r + dr, cc = c + dc;
-        th[m] = 0.f;
-        if (rr >= 0 && rr < J.H && cc >= 0 && cc < J.W)
-            th[m] = slope_deg(J, Ej, J.elev[(int64_t)rr * J.W + cc], dr, dc);
+        for (int m = 0; m < 8; ++m) {
+            int dr, dc;
+            slot_dir(m, dr, dc);
+            th[m] = slope9[j * 9 + (dr + 1) * 3 + (dc + 1)];
+            bad |= !isfinite(th[m]);
+        }
+        if (bad) atomicOr(err, 64);
+    } else {
+        const float Ej = J.elev[j];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            int dr, dc;
+            slot_dir(m, dr, dc);
+            const int rr = r + dr, cc = c + dc;
+            th[m] = 0.f;
+            if (rr >= 0 && rr < J.H && cc >= 0 && cc < J.W)
+                th[m] = slope_deg(J, Ej, J.elev[(int64_t)rr * J.W + cc], dr, dc);
+        }
     }
     float4* o = reinterpret_cast<float4*>(th8 + j * 8);
     o[0] = make_float4(th[0], th[1], th[2], th[3]);
@@ -710,6 +724,94 @@ k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, in
     o[1] = make_float4(q[4], q[5], q[6], q[7]);
 }
 
+// ------------------------------------------------ wind, spotting, metrics
+
+// New wind for one scenario: (V, V cos(theta_w), V sin(theta_w)) of rec.
+__global__ void __launch_bounds__(256)
+k_set_wind(int32_t H, int32_t W, const float* __restrict__ ws, const float* __restrict__ wd,
+           float ws0, float wd0, float4* __restrict__ rec, int* __restrict__ err) {
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= W) return;
+    const int64_t j = (int64_t)r * W + c;
+    const float V = ws ? ws[j] : ws0;
+    const float th = wd ? wd[j] : wd0;
+    if (!(V >= 0.f) || !isfinite(V) || !isfinite(th)) atomicOr(err, 8);
+    float sn, cs;
+    sincospif(th / 180.f, &sn, &cs);
+    float4 v = rec[j];
+    v.y = V;
+    v.z = V * cs;
+    v.w = V * sn;
+    rec[j] = v;
+}
+
+// Spotting: listed cells become burning (unless burned) in both buffers.
+__global__ void __launch_bounds__(256)
+k_ignite(DevScen J, const int32_t* __restrict__ cells, int32_t count) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= count) return;
+    const int64_t j = cells[i];
+    if (j < 0 || j >= (int64_t)J.H * J.W) return;
+    const int r = (int)(j / J.W), c = (int)(j - (int64_t)r * J.W);
+    const int64_t o = (int64_t)r * J.pitch + (c >> 5);
+    const int64_t PW = (int64_t)J.H * J.pitch;
+    const uint32_t bit = 1u << (c & 31);
+    for (int b = 0; b < 2; ++b) {
+        uint32_t* p = J.planes[b];
+        if (!(p[PW + o] & bit)) atomicOr(&p[o], bit);
+    }
+}
+
+// Burning / burned counts per job: popcount over the bit-planes.
+__global__ void __launch_bounds__(256)
+k_counts(const DevScen* __restrict__ jobs, int32_t parity, long long* __restrict__ out) {
+    const DevScen& J = jobs[blockIdx.y];
+    const int64_t PW = (int64_t)J.H * J.pitch;
+    const uint32_t* B = J.planes[parity];
+    long long nb = 0, nd = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < PW; i += (int64_t)gridDim.x * 256) {
+        nb += __popc(B[i]);
+        nd += __popc(B[PW + i]);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        nb += __shfl_down(nb, d, 64);
+        nd += __shfl_down(nd, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (nb) atomicAdd((unsigned long long*)&out[2 * blockIdx.y], (unsigned long long)nb);
+        if (nd) atomicAdd((unsigned long long*)&out[2 * blockIdx.y + 1], (unsigned long long)nd);
+    }
+}
+
+// |A & B| and |A | B| for affected cells A (burning or burned) and target B.
+__global__ void __launch_bounds__(256)
+k_overlap(DevScen J, int32_t parity, const uint8_t* __restrict__ target,
+          long long* __restrict__ out) {
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    long long in = 0, un = 0;
+    if (c < J.W) {
+        const int64_t o = (int64_t)r * J.pitch + (c >> 5);
+        const int64_t PW = (int64_t)J.H * J.pitch;
+        const uint32_t* B = J.planes[parity];
+        const bool a = ((B[o] | B[PW + o]) >> (c & 31)) & 1u;
+        const bool b = target[(int64_t)r * J.W + c] != 0;
+        in = a && b;
+        un = a || b;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        in += __shfl_down(in, d, 64);
+        un += __shfl_down(un, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (in) atomicAdd((unsigned long long*)&out[0], (unsigned long long)in);
+        if (un) atomicAdd((unsigned long long*)&out[1], (unsigned long long)un);
+    }
+}
+
 // ------------------------------------------------------------- prologue
 
 // One thread per cell of the padded grid (H rows x pitch*32 columns); a
@@ -727,7 +829,7 @@ k_prologue(int32_t H, int32_t W, int32_t pitch, const float* __restrict__ p_veg,
     bool has_fuel = false, burning = false;
     if (c < W) {
         const int64_t j = (int64_t)r * W + c;
-        const float pv = p_veg[j], pd = p_den[j], e = elev[j];
+        const float pv = p_veg[j], pd = p_den[j], e = elev ? elev[j] : 0.f;
         const float V = ws ? ws[j] : ws0;
         const float th = wd ? wd[j] : wd0;
         int bad = 0;
@@ -1177,8 +1279,39 @@ hipError_t launch_prologue(hipStream_t st, const DevScen* /*d_job*/, const DevSc
     return hipGetLastError();
 }
 
-hipError_t launch_slopes(hipStream_t st, const DevScen& J, float* th8) {
-    hipLaunchKernelGGL(k_slopes, cell_grid(J.H, J.W), dim3(256), 0, st, J, th8);
+hipError_t launch_slopes(hipStream_t st, const DevScen& J, float* th8, const float* slope9,
+                         int* d_err) {
+    hipLaunchKernelGGL(k_slopes, cell_grid(J.H, J.W), dim3(256), 0, st, J, th8, slope9, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_wind(hipStream_t st, const DevScen& J, const float* ws, const float* wd,
+                           float ws0, float wd0, float4* rec, int* d_err) {
+    hipLaunchKernelGGL(k_set_wind, cell_grid(J.H, J.W), dim3(256), 0, st, J.H, J.W, ws, wd, ws0,
+                       wd0, rec, d_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_ignite(hipStream_t st, const DevScen& J, const int32_t* cells, int32_t count) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ignite, dim3((count + 255) / 256), dim3(256), 0, st, J, cells, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_counts(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
+                         int64_t max_words, long long* out) {
+    hipError_t e = launch_fill_u32(st, reinterpret_cast<uint32_t*>(out), (size_t)n * 4, 0u);
+    if (e != hipSuccess || n <= 0) return e;
+    const unsigned gx = (unsigned)std::min<int64_t>((max_words + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_counts, dim3(gx, n), dim3(256), 0, st, d_jobs, parity, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_overlap(hipStream_t st, const DevScen& J, int32_t parity, const uint8_t* target,
+                          long long* out) {
+    hipError_t e = launch_fill_u32(st, reinterpret_cast<uint32_t*>(out), 4, 0u);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_overlap, cell_grid(J.H, J.W), dim3(256), 0, st, J, parity, target, out);
     return hipGetLastError();
 }
 

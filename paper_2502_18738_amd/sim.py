@@ -60,11 +60,20 @@ class Sim:
             pv, pd, el = f32(s.p_veg), f32(s.p_den), f32(s.elevation)
             ws, wd = f32(s.wind_speed), f32(s.wind_dir)
             ign = _dev_tensor(s.init_burning, torch.uint8, self.device)
-            self._keep += [pv, pd, el, ws, wd, ign]
+            sl = f32(getattr(s, "slope_deg", None))
+            hw = int(s.H) * int(s.W)
+            for name, t, k in (("p_veg", pv, 1), ("p_den", pd, 1), ("elevation", el, 1),
+                               ("wind_speed", ws, 1), ("wind_dir", wd, 1),
+                               ("init_burning", ign, 1), ("slope_deg", sl, 9)):
+                if t is not None and t.numel() != k * hw:
+                    raise ValueError(f"scenario {i}: {name} holds {t.numel()} values, "
+                                     f"expected {k * hw}")
+            self._keep += [pv, pd, el, ws, wd, ign, sl]
             fields = _abi.sim_fields(
-                pv.data_ptr(), pd.data_ptr(), el.data_ptr(),
+                pv.data_ptr(), pd.data_ptr(), None if el is None else el.data_ptr(),
                 None if ws is None else ws.data_ptr(), None if wd is None else wd.data_ptr(),
-                float(s.wind_speed_scalar), float(s.wind_dir_scalar), ign.data_ptr())
+                float(s.wind_speed_scalar), float(s.wind_dir_scalar), ign.data_ptr(),
+                None if sl is None else sl.data_ptr())
             par = _abi.sim_params(*(float(np.float32(getattr(s, k)))
                                     for k in ("p_h", "a", "c1", "c2", "p_continue")))
             descs[i] = _abi.sim_desc(int(s.H), int(s.W), float(s.cell_m),
@@ -210,6 +219,43 @@ class Sim:
         grad = torch.empty((self.n, 4), dtype=torch.float64, device=self.device)
         self._check(self._lib.sim_loss_grad(self._h, _ptr(y), int(kind), _ptr(loss), _ptr(grad)))
         return loss, grad
+
+    def set_wind(self, s: int, wind_speed=None, wind_dir=None, speed_scalar=0.0, dir_scalar=0.0):
+        """New wind for scenario s (fields H x W, or None for the scalars)."""
+        ws = _dev_tensor(wind_speed, torch.float32, self.device)
+        wd = _dev_tensor(wind_dir, torch.float32, self.device)
+        hw = self.shapes[s][0] * self.shapes[s][1] if 0 <= s < self.n else 0
+        for t in (ws, wd):
+            if t is not None and t.numel() != hw:
+                raise ValueError("wind fields must hold H*W values of scenario s")
+        self._check(self._lib.sim_set_wind(self._h, int(s), _ptr(ws), _ptr(wd),
+                                           float(speed_scalar), float(dir_scalar)))
+
+    def ignite(self, s: int, cells):
+        """Spotting: set cells (flat r*W + c indices) burning before the next step."""
+        c = _dev_tensor(np.asarray(cells, dtype=np.int32) if not isinstance(cells, torch.Tensor)
+                        else cells, torch.int32, self.device).view(-1)
+        self._check(self._lib.sim_ignite(self._h, int(s), _ptr(c), int(c.numel())))
+
+    def counts(self) -> torch.Tensor:
+        """(n, 2) int64 device tensor: burning and burned cells per scenario."""
+        out = torch.empty((self.n, 2), dtype=torch.int64, device=self.device)
+        self._check(self._lib.sim_counts(self._h, _ptr(out)))
+        return out
+
+    def overlap(self, s: int, target) -> torch.Tensor:
+        """(|A & B|, |A | B|) of scenario s's affected cells and a target mask."""
+        y = _dev_tensor(target, torch.uint8, self.device)
+        if not 0 <= s < self.n or y.numel() != self.shapes[s][0] * self.shapes[s][1]:
+            raise ValueError("target must hold H*W values of scenario s")
+        out = torch.empty(2, dtype=torch.int64, device=self.device)
+        self._check(self._lib.sim_overlap(self._h, int(s), _ptr(y), _ptr(out)))
+        return out
+
+    def jaccard(self, s: int, target) -> float:
+        """Eq. 11 against a target affected-area mask."""
+        i, u = (int(x) for x in self.overlap(s, target).cpu())
+        return 1.0 if u == 0 else i / u
 
     def stats(self) -> dict:
         v = (ctypes.c_uint64 * 4)()

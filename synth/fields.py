@@ -70,6 +70,9 @@ class Scenario:
     seed: int = 0
     scenario_id: int = 0
     T: int = 100
+    # Optional per-edge slope angles in degrees, H x W x 3 x 3 (the paper's
+    # slope tensor layout); when given it replaces the elevation-based Eq. 1.
+    slope_deg: Optional[np.ndarray] = None
 
     @property
     def params(self):

@@ -40,13 +40,13 @@ def test_library_exports_every_declared_symbol(lib):
 def test_struct_layout_matches_header():
     # sizes follow from the header's field order on LP64
     assert ctypes.sizeof(_abi.sim_params) == 20
-    assert ctypes.sizeof(_abi.sim_fields) == 56
-    assert ctypes.sizeof(_abi.sim_desc) == 24 + 20 + 4 + 56
+    assert ctypes.sizeof(_abi.sim_fields) == 64
+    assert ctypes.sizeof(_abi.sim_desc) == 24 + 20 + 4 + 64
     assert ctypes.sizeof(_abi.sim_exec) == 16
 
 
 def fake_desc(H=64, W=80, **kw):
-    f = _abi.sim_fields(0x1000, 0x2000, 0x3000, None, None, 5.0, 45.0, 0x4000)
+    f = _abi.sim_fields(0x1000, 0x2000, 0x3000, None, None, 5.0, 45.0, 0x4000, None)
     p = _abi.sim_params(0.58, 0.078, 0.045, 0.131, 0.3)
     d = _abi.sim_desc(H, W, 30.0, 0, 1, p, f)
     for k, v in kw.items():

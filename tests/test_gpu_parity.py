@@ -14,6 +14,7 @@ The oracle never receives anything the GPU produced: every GPU run starts from
 inputs the generators or the oracle made.
 """
 
+import dataclasses
 import numpy as np
 import pytest
 from scipy.ndimage import maximum_filter
@@ -459,3 +460,98 @@ def test_adjoint_methods_and_step_rings_match_oracle(Sim, rings):
         for method in grads:
             gg = grads[method][b]
             assert np.all(np.abs(gg - g) <= 1e-4 * np.abs(g) + 1e-5 * scale), (method, gg, g)
+
+
+# ------------------------------- slope tensor, wind updates, spotting, metrics
+
+def test_slope_tensor_input_matches_oracle(Sim):
+    s, S = front_case("lakes", 90, 130, 61)
+    s.slope_deg = oracle.slope_tensor(s)
+    ref = oracle.pignite_map(dataclasses.replace(s), S)
+    t = dataclasses.replace(s)
+    t.elevation = None
+    sim = Sim([t])
+    sim.set_state(0, synth.encode_planes(S), 0)
+    p = sim.pignite(0).cpu().numpy().astype(np.float64)
+    nz = ref > 0
+    assert np.all(p[~nz] == 0.0)
+    assert np.max(np.abs(p[nz] - ref[nz]) / ref[nz]) <= 1e-5
+    states, ties = oracle_traj(t, 20, S0=S)
+    sim.run(20)
+    check_light_cone(gstate(sim), states, ties, 20)
+
+
+def test_set_wind_equals_a_fresh_scenario(Sim):
+    s = synth.make_lakes(100, 140, 62, T=40)
+    w = synth.make_lakes(100, 140, 63, T=40)
+    a = Sim([s])
+    a.set_wind(0, w.wind_speed, w.wind_dir)
+    a.run(40)
+    fresh = dataclasses.replace(s)
+    fresh.wind_speed, fresh.wind_dir = w.wind_speed, w.wind_dir
+    b = Sim([fresh])
+    b.run(40)
+    assert np.array_equal(a.get_state(0).cpu().numpy(), b.get_state(0).cpu().numpy())
+    c = Sim([s])
+    c.set_wind(0, None, None, 7.0, 200.0)          # scalar wind
+    c.run(40)
+    scal = dataclasses.replace(s)
+    scal.wind_speed = scal.wind_dir = None
+    scal.wind_speed_scalar, scal.wind_dir_scalar = 7.0, 200.0
+    d = Sim([scal])
+    d.run(40)
+    assert np.array_equal(c.get_state(0).cpu().numpy(), d.get_state(0).cpu().numpy())
+
+
+def test_spotting_matches_oracle(Sim):
+    """Extra ignitions injected in place between steps (Sec. 2.2) behave like
+    initial ignition points: the oracle continues from the same patched state."""
+    s = synth.make_lakes(120, 110, 64, T=60)
+    states, _ = oracle_traj(s, 30)
+    S30 = states[30].copy()
+    rng = np.random.default_rng(5)
+    cells = rng.choice(s.H * s.W, size=25, replace=False)
+    patched = S30.copy().ravel()
+    patched[cells] = np.where(patched[cells] == 2, 2, 1)
+    patched = patched.reshape(S30.shape)
+    ref, ties = oracle_traj(s, 30, S0=patched, t0=30)
+    sim = Sim([s])
+    sim.set_state(0, synth.encode_planes(S30), 30)
+    sim.ignite(0, np.concatenate([cells, [-5, s.H * s.W + 3]]))   # invalid ones ignored
+    assert np.array_equal(gstate(sim), patched)
+    sim.run(30)
+    check_light_cone(gstate(sim), ref, ties, 30)
+
+
+def test_counts_and_overlap(Sim):
+    scs = [synth.make_lakes(70, 90, 65, T=30), synth.make_plain(50, 33, 66, T=30)]
+    sim = Sim(scs)
+    sim.run(30)
+    c = sim.counts().cpu().numpy()
+    for b in range(2):
+        g = gstate(sim, b)
+        assert c[b, 0] == np.count_nonzero(g == 1) and c[b, 1] == np.count_nonzero(g == 2)
+        tgt = (oracle.run(scs[b], 30, seed=999)["S"] != 0).astype(np.uint8)
+        assert sim.jaccard(b, tgt) == pytest.approx(oracle.jaccard(g != 0, tgt != 0), abs=0)
+
+
+def test_calibrate_sequence_mechanics(Sim):
+    from paper_2502_18738_amd.calib import calibrate_sequence
+    s = synth.make_lakes(96, 96, 67, T=60, n_ignitions=2)
+    obs = []
+    for it in range(3):
+        r = oracle.run(s, 20 * (it + 1), seed=4242)
+        obs.append((r["S"] != 0).astype(np.uint8).ravel())
+    winds = [[(None, None, 3.0 + it, 30.0 * it)] for it in range(3)]
+    start = s.with_params(0.8, 0.1, 0.06, 0.2)
+    runs = []
+    for _ in range(2):
+        sim = Sim([start], calib=True, T_max=60, ckpt_every=10)
+        theta, hist = calibrate_sequence(sim, obs, [[0.8, 0.1, 0.06, 0.2]], interval=20,
+                                         epochs=2, lr=1e-2, winds=winds)
+        assert [(h[0], h[1]) for h in hist] == [(e, i) for e in range(2) for i in range(3)]
+        for h in hist:
+            th = h[3].numpy()[0]
+            assert 0.2 <= th[0] <= 1.0 and np.all(th[1:] >= 0) and np.all(th <= 1)
+        runs.append(theta.cpu().numpy())
+    assert np.array_equal(runs[0], runs[1])

@@ -6,6 +6,7 @@ known-answer vector, an independent implementation (rocRAND's header-only
 Philox engine), an invariant of the transition rules, or finite differences.
 """
 
+import dataclasses
 import json
 import math
 import os
@@ -440,3 +441,39 @@ def test_gradient_vanishing_cases(oracle_lib):
     g = oracle_lib.grad(s, 12, lam)
     assert g[1] == 0.0 and g[2] == 0.0 and g[3] == 0.0
     assert g[0] != 0.0
+
+
+# ------------------------------------------ slope tensor input, Eq. 11-12
+
+def test_slope_tensor_layout_and_equivalence(oracle_lib):
+    """The paper-layout slope tensor puts Eq. 1's angle of the edge
+    (r+dr, c+dc) -> (r, c) at [r][c][dr+1][dc+1]; feeding it back reproduces
+    the elevation-based p_ignite (up to the FP32 rounding of the angles)."""
+    s = flat_scenario(3, 3)
+    E = np.zeros((3, 3), np.float32)
+    E[1, 1] = 30.0                      # the centre is l metres above the west cell
+    s.elevation = E
+    t = oracle_lib.slope_tensor(s)
+    assert t[1, 1, 1, 0] == pytest.approx(45.0, abs=1e-5)
+    assert t[1, 1, 1, 1] == 0.0
+    assert t[1, 0, 1, 2] == pytest.approx(-45.0, abs=1e-5)   # west cell, from the centre
+    assert t[0, 0, 0, 0] == 0.0                               # out-of-grid slot
+    s2, S = random_small(17, 23, 31, per_cell_wind=True)
+    ref = oracle_lib.pignite_map(s2, S)
+    s3 = dataclasses.replace(s2)
+    s3.slope_deg = oracle_lib.slope_tensor(s2)
+    s3.elevation = None
+    got = oracle_lib.pignite_map(s3, S)
+    np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-12)
+
+
+def test_jaccard_and_manhattan_closed_forms(oracle_lib):
+    A = np.zeros((4, 4), bool)
+    B = np.zeros((4, 4), bool)
+    A[:2, :2] = True
+    B[1:3, 1:3] = True
+    assert oracle_lib.jaccard(A, A) == 1.0
+    assert oracle_lib.jaccard(A, ~A) == 0.0
+    assert oracle_lib.jaccard(A, B) == pytest.approx(1 / 7)
+    assert oracle_lib.manhattan([1, 5, 9], [2, 5, 7]) == 3.0
+    assert oracle_lib.manhattan([3, 3], [3, 3]) == 0.0
