@@ -248,6 +248,13 @@ SIM_API int sim_counts(sim_handle* h, int64_t* out);
  * (|A intersect B|, |A union B|); Eq. 11's Jaccard index is their ratio. */
 SIM_API int sim_overlap(sim_handle* h, int32_t s, const uint8_t* target, int64_t* out);
 
+/* Probability of arrival from an ensemble of runs (Sec. 1): counts[j] (device
+ * uint32 H*W, zeroed by the caller) += the number of scenarios s0 .. s0+n-1
+ * in which cell j is affected (burning or burned).  The n scenarios must share
+ * one grid shape (SIM_E_SHAPE otherwise); typically they differ only in seed.
+ * counts / (number of runs accumulated) is the arrival-probability map. */
+SIM_API int sim_arrival(sim_handle* h, int32_t s0, int32_t n, uint32_t* counts);
+
 /* Counters accumulated since the last reset with SIM_F_STATS (host array of
  * 4): processed tiles, ignition + continue trials, ignition trials with
  * |draw - p_ignite| <= 1e-5, launches. */

@@ -33,6 +33,8 @@
  *                         common random numbers; vanishing-derivative cases)
  *   fo_loss               pinned (closed forms on hand-made maps; finite
  *                         differences of the loss for lambda)
+ *   fo_slope_tensor       pinned (hand-computed 45 degree edges, sign and
+ *                         layout; equivalence with the elevation path)
  */
 #ifndef FIREORACLE_H
 #define FIREORACLE_H
@@ -67,6 +69,13 @@ void fo_draws(const fo_problem* pb, int32_t t, int64_t cell, double* u_ign, doub
  * spreading into cell (r, c).  Optional outputs: theta_s (deg), cos(delta). */
 double fo_edge_q(const fo_problem* pb, int32_t r, int32_t c, int32_t dr, int32_t dc,
                  double* theta_s_out, double* cosd_out);
+
+/* Eq. 1 angles in the paper's slope-tensor layout: out9[(r*W + c)*9 +
+ * (dr+1)*3 + (dc+1)] = angle (degrees, FP32) of the edge from the neighbour
+ * (r+dr, c+dc) into (r, c); 0 for the centre and out-of-grid slots.  Needs
+ * pb->elev.  Feeding the result back as pb->slope9 reproduces the
+ * elevation-based model up to the FP32 rounding of the angles. */
+void fo_slope_tensor(const fo_problem* pb, float* out9);
 
 /* Eq. 9 for cell (r, c) of state S; 0 for cells that are not burnable. */
 double fo_pignite_cell(const fo_problem* pb, const uint8_t* S, int32_t r, int32_t c);

@@ -15,13 +15,14 @@ from ._abi import (  # noqa: F401
     load,
 )
 
-__all__ = ["load", "Sim", "SimError", "FireCalib", "calibrate", "calibrate_sequence"]
+__all__ = ["load", "Sim", "SimError", "FireCalib", "calibrate", "calibrate_sequence",
+           "ensemble_arrival"]
 
 
 def __getattr__(name):
-    if name == "Sim":
-        from .sim import Sim
-        return Sim
+    if name in ("Sim", "ensemble_arrival"):
+        from . import sim
+        return getattr(sim, name)
     if name in ("FireCalib", "calibrate", "calibrate_sequence"):
         from . import calib
         return getattr(calib, name)

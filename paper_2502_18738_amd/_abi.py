@@ -65,7 +65,7 @@ EXPORTS = (
     "sim_get_step", "sim_set_params", "sim_reset", "sim_get_state", "sim_set_state",
     "sim_pignite", "sim_accumulator", "sim_adjoint", "sim_loss_grad", "sim_stats",
     "sim_last_error", "sim_destroy", "sim_version", "sim_autotune", "sim_use_graphs",
-    "sim_set_adjoint", "sim_set_wind", "sim_ignite", "sim_counts", "sim_overlap",
+    "sim_set_adjoint", "sim_set_wind", "sim_ignite", "sim_counts", "sim_overlap", "sim_arrival",
 )
 
 _lib = None
@@ -114,6 +114,7 @@ def load():
         "sim_ignite": (ctypes.c_int, [H, i32, vp, i32]),
         "sim_counts": (ctypes.c_int, [H, vp]),
         "sim_overlap": (ctypes.c_int, [H, i32, vp, vp]),
+        "sim_arrival": (ctypes.c_int, [H, i32, i32, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

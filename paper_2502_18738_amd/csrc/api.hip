@@ -1048,6 +1048,18 @@ int sim_overlap(sim_handle* h, int32_t s, const uint8_t* target, int64_t* out) {
                                      reinterpret_cast<long long*>(out)), "overlap");
 }
 
+int sim_arrival(sim_handle* h, int32_t s0, int32_t n, uint32_t* counts) {
+    if (!h) return SIM_E_ARG;
+    if (!counts || ((uintptr_t)counts & 3u)) return h->fail(SIM_E_ARG, "counts must be a 4-byte aligned device pointer");
+    if (s0 < 0 || n < 1 || (int64_t)s0 + n > h->n)
+        return h->fail(SIM_E_ARG, "scenario range [%d, %d) outside [0, %d)", s0, s0 + n, h->n);
+    for (int s = s0 + 1; s < s0 + n; ++s)
+        if (h->job[s].H != h->job[s0].H || h->job[s].W != h->job[s0].W)
+            return h->fail(SIM_E_SHAPE, "scenario %d has a different grid shape than %d", s, s0);
+    return h->hip(fs::launch_arrival(h->st, h->d_jobs(), h->job[s0], s0, n, h->parity, counts),
+                  "arrival counts");
+}
+
 int sim_stats(sim_handle* h, uint64_t out[4]) {
     if (!h || !out) return SIM_E_ARG;
     unsigned long long v[4] = {0, 0, 0, 0};

@@ -92,6 +92,9 @@ hipError_t launch_ignite(hipStream_t st, const DevScen& job, const int32_t* cell
 hipError_t launch_counts(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
                          int64_t max_words, long long* out);
 // out = (|A & B|, |A | B|) for affected cells A of one job and target B.
+// counts[j] += scenarios s0 .. s0+n-1 (shape of J0 = job s0) in which j is affected
+hipError_t launch_arrival(hipStream_t st, const DevScen* d_jobs, const DevScen& J0, int32_t s0,
+                          int32_t n, int32_t parity, uint32_t* counts);
 hipError_t launch_overlap(hipStream_t st, const DevScen& job, int32_t parity, const uint8_t* target,
                           long long* out);
 // Propagation table q8 of every scenario for the current parameters.

@@ -37,14 +37,13 @@ __device__ __forceinline__ void philox_w01(uint32_t c0, uint32_t c1, uint32_t c2
                                            uint32_t& w0, uint32_t& w1) {
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        c0 = hi1 ^ c1 ^ k0;
-        c1 = lo1;
-        c2 = hi0 ^ c3 ^ k1;
-        c3 = lo0;
+        // one 32 x 32 -> 64-bit product per multiplier gives both halves
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        c1 = (uint32_t)p1;
+        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -53,6 +52,24 @@ __device__ __forceinline__ void philox_w01(uint32_t c0, uint32_t c1, uint32_t c2
 }
 
 __device__ __forceinline__ float u24(uint32_t w) { return (float)(w >> 8) * kTwoM24; }
+
+// Global-memory view of a pointer read from a descriptor.  The compiler cannot
+// infer the address space of such pointers and would use generic (flat)
+// accesses, which also count against the LDS wait counter: every LDS wait of
+// the step loop would then wait for outstanding HBM reads as well.
+#define FS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ FS_GLOBAL T* gmem(T* p) {
+    return (FS_GLOBAL T*)p;
+}
+
+// 16-byte vector read through a global pointer (HIP's float4 cannot be copied
+// out of a non-generic address space).
+typedef float fs_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 load_f4(const void* base, int64_t i) {
+    const fs_f4 v = ((const FS_GLOBAL fs_f4*)base)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
 
 // Neighbour slot e = 0..7 walks the 3 x 3 block row by row, skipping the
 // centre: (dr, dc) = (-1,-1), (-1,0), (-1,1), (0,-1), (0,1), (1,-1), (1,0), (1,1).
@@ -147,7 +164,8 @@ __device__ __forceinline__ bool attached(const Rings& rg, int t) {
 // dx/d(p_h, a, c1, c2) = (F e^z, x theta_s, x V, x V (cos - 1)).
 template <class NB>
 __device__ __forceinline__ float pignite_grad(const DevScen& J, int64_t j, NB nb, float gl[4]) {
-    const float4 rec = J.rec[j];
+    const float4 rec = load_f4(J.rec, j);
+    const FS_GLOBAL float* th8 = gmem(J.th8);
     float q[8], dx[8][4];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -156,7 +174,7 @@ __device__ __forceinline__ float pignite_grad(const DevScen& J, int64_t j, NB nb
         q[m] = 0.f;
         dx[m][0] = dx[m][1] = dx[m][2] = dx[m][3] = 0.f;
         if (nb(dr, dc)) {
-            const Edge ed = edge_terms(J, rec, J.th8[j * 8 + m], dr, dc);
+            const Edge ed = edge_terms(J, rec, th8[j * 8 + m], dr, dc);
             q[m] = ed.q;
             dx[m][0] = rec.x * ed.ez;
             dx[m][1] = ed.x * ed.th;
@@ -181,15 +199,24 @@ __device__ __forceinline__ float pignite_grad(const DevScen& J, int64_t j, NB nb
     return P;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wavefront with DPP lane moves
+// (shifts inside 16-lane rows, then the row-15 and row-31 broadcasts), so the
+// scan costs six register-to-register moves instead of LDS permutes.  Every
+// lane of the wavefront must be active.
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
+}
+
 template <int NWAVE>
 __device__ __forceinline__ int block_exscan(int v, int* sWave, int* total) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+    const int x = wave_incl_scan(v);
     if (lane == 63) sWave[wv] = x;
     __syncthreads();
     int pre = 0, tot = 0;
@@ -202,6 +229,37 @@ __device__ __forceinline__ int block_exscan(int v, int* sWave, int* total) {
     *total = tot;
     __syncthreads();
     return pre + x - v;
+}
+
+// Exclusive prefix sums of two per-thread values over the work-group in one
+// pass (sWave holds 2 * NWAVE ints); returns the prefix of v, sets the prefix
+// of u and both totals.  Ends without a barrier: the caller must synchronise
+// before sWave is written again.
+template <int NWAVE>
+__device__ __forceinline__ int block_exscan2(int v, int u, int* sWave, int* tot_v, int* pre_u,
+                                             int* tot_u) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = wave_incl_scan(v), y = wave_incl_scan(u);
+    if (lane == 63) {
+        sWave[wv] = x;
+        sWave[NWAVE + wv] = y;
+    }
+    __syncthreads();
+    int pv = 0, tv = 0, pu = 0, tu = 0;
+#pragma unroll
+    for (int k = 0; k < NWAVE; ++k) {
+        const int s = sWave[k], t = sWave[NWAVE + k];
+        if (k < wv) {
+            pv += s;
+            pu += t;
+        }
+        tv += s;
+        tu += t;
+    }
+    *tot_v = tv;
+    *tot_u = tu;
+    *pre_u = pu + y - u;
+    return pv + x - v;   // the caller barriers before sWave is written again
 }
 
 // XCD-aware tile order: consecutive workgroups are dealt round-robin to the 8
@@ -232,7 +290,13 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
 
     __shared__ uint32_t sB[2][NW], sD[2][NW], sU[NW], sR[NW];
     __shared__ uint16_t sL[LCAP];
-    __shared__ int sWave[NWAVE];
+    // words holding a trial this step: (word index, continue mask, ignition
+    // mask, offsets of their first list entries: continue | ignition << 16)
+    __shared__ uint4 sWL[NW];
+    // forward: per word, which of the 8 neighbour slots of each of its 32
+    // cells burn (one mask per slot), written for words with ignition trials
+    __shared__ uint4 sN[ADJ ? 1 : NW][2];
+    __shared__ int sWave[2 * NWAVE];
     __shared__ int sFlag;
     __shared__ double sG[ADJ ? NWAVE * 4 : 1];
 
@@ -242,17 +306,18 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     // previous launch marked (worklist: a fixed grid walks the set bits)
     __shared__ int sItems, sTile;
     const bool listed = sched.in != nullptr;
+    const FS_GLOBAL unsigned long long* sin = gmem(sched.in);
     int my_pre = 0, my_cnt = 0, my_w0 = 0, my_w1 = 0;
     if (listed) {
         const int wpt = (sched.nwords + NT - 1) / NT;
         my_w0 = min(sched.nwords, tid * wpt);
         my_w1 = min(sched.nwords, my_w0 + wpt);
-        for (int w = my_w0; w < my_w1; ++w) my_cnt += __popcll(sched.in[w]);
+        for (int w = my_w0; w < my_w1; ++w) my_cnt += __popcll(sin[w]);
         int tot;
         my_pre = block_exscan<NWAVE>(my_cnt, sWave, &tot);
         if (tid == 0) sItems = tot;
         for (int w = blockIdx.x * NT + tid; w < sched.nwords; w += gridDim.x * NT)
-            sched.clear[w] = 0ull;
+            gmem(sched.clear)[w] = 0ull;
         __syncthreads();
     }
     const int nitems = listed ? sItems : 1;
@@ -263,7 +328,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         if (it >= my_pre && it < my_pre + my_cnt) {
             int k = it - my_pre;
             for (int w = my_w0; w < my_w1; ++w) {
-                unsigned long long m = sched.in[w];
+                unsigned long long m = sin[w];
                 const int c = __popcll(m);
                 if (k < c) {
                     for (int q = 0; q < k; ++q) m &= m - 1;
@@ -284,10 +349,12 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     const int trow = lt / J.tiles_c, tcol = lt - trow * J.tiles_c;
     const int H = J.H, pitch = J.pitch;
     const int64_t PW = (int64_t)H * pitch;
-    const uint8_t* fin = J.flags[parity];
-    uint8_t* fout = J.flags[parity ^ 1];
-    const uint32_t* pin = J.planes[parity];
-    uint32_t* pout = J.planes[parity ^ 1];
+    const FS_GLOBAL uint8_t* fin = gmem(J.flags[parity]);
+    FS_GLOBAL uint8_t* fout = gmem(J.flags[parity ^ 1]);
+    const FS_GLOBAL uint32_t* pin = gmem(J.planes[parity]);
+    FS_GLOBAL uint32_t* pout = gmem(J.planes[parity ^ 1]);
+    const FS_GLOBAL uint32_t* fuel = gmem(J.fuel);
+    const FS_GLOBAL float* q8g = gmem(J.q8);
 
     const int kj = min(ksteps, J.t_end - (J.t_base + t_off));
     if (kj <= 0) continue;
@@ -335,7 +402,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 const int64_t o = (int64_t)gr * pitch + gw;
                 b = pin[o];
                 d = pin[PW + o];
-                u = J.fuel[o];
+                u = fuel[o];
             }
             sB[0][w] = b;
             sD[0][w] = d;
@@ -362,6 +429,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         // and ignition trials (burnable cells with fuel and a burning neighbour)
         uint32_t mc[WPT], mi[WPT];
         int cnt = 0;  // continue count | ignition count << 16
+        int nne = 0;  // words of this thread with a trial
 #pragma unroll
         for (int i = 0; i < WPT; ++i) {
             const int w = tid + i * NT;
@@ -369,42 +437,71 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             if (w < NW) {
                 const int lr = w / RC, lc = w - (w / RC) * RC;
                 if (lr >= lo && lr < hi) {
+                    // burning-neighbour masks per slot (slot order of slot_dir):
+                    // bit b of slot (dr, dc) = cell (lr + dr, 32 lc + b + dc) burns
                     const int a = (lr - 1) * RC, b = lr * RC, c = (lr + 1) * RC;
-                    const uint32_t X = cB[a + lc] | cB[b + lc] | cB[c + lc];
-                    const uint32_t XL = lc > 0 ? (cB[a + lc - 1] | cB[b + lc - 1] | cB[c + lc - 1]) : 0u;
-                    const uint32_t XR = lc < RC - 1 ? (cB[a + lc + 1] | cB[b + lc + 1] | cB[c + lc + 1]) : 0u;
-                    const uint32_t nbm = X | (X << 1) | (X >> 1) | (XL >> 31) | (XR << 31);
-                    const uint32_t bw = cB[w], dw = cD[w];
-                    mc[i] = bw;
-                    mi[i] = nbm & ~bw & ~dw & sU[w];
+                    const uint32_t up = cB[a + lc], mid = cB[b + lc], dn = cB[c + lc];
+                    uint32_t upL = 0, midL = 0, dnL = 0, upR = 0, midR = 0, dnR = 0;
+                    if (lc > 0) {
+                        upL = cB[a + lc - 1];
+                        midL = cB[b + lc - 1];
+                        dnL = cB[c + lc - 1];
+                    }
+                    if (lc < RC - 1) {
+                        upR = cB[a + lc + 1];
+                        midR = cB[b + lc + 1];
+                        dnR = cB[c + lc + 1];
+                    }
+                    const uint32_t n0 = (up << 1) | (upL >> 31), n1 = up,
+                                   n2 = (up >> 1) | (upR << 31);
+                    const uint32_t n3 = (mid << 1) | (midL >> 31), n4 = (mid >> 1) | (midR << 31);
+                    const uint32_t n5 = (dn << 1) | (dnL >> 31), n6 = dn,
+                                   n7 = (dn >> 1) | (dnR << 31);
+                    const uint32_t nbm = n0 | n1 | n2 | n3 | n4 | n5 | n6 | n7;
+                    const uint32_t dw = cD[w];
+                    mc[i] = mid;
+                    mi[i] = nbm & ~mid & ~dw & sU[w];
                     cnt += __popc(mc[i]) | (__popc(mi[i]) << 16);
+                    nne += (mc[i] | mi[i]) != 0u;
                     sR[w] = 0;
+                    if constexpr (!ADJ) {
+                        if (mi[i]) {
+                            sN[w][0] = make_uint4(n0, n1, n2, n3);
+                            sN[w][1] = make_uint4(n4, n5, n6, n7);
+                        }
+                    }
                 }
             }
         }
-        int tot;
-        const int off = block_exscan<NWAVE>(cnt, sWave, &tot);
+        int tot, pre_w, tot_w;
+        const int off = block_exscan2<NWAVE>(cnt, nne, sWave, &tot, &pre_w, &tot_w);
         const int tot_c = tot & 0xFFFF, tot_i = tot >> 16;
 
-        // compacted trial list: continue entries first, then ignition entries
+        // compacted trial list, continue entries first, then ignition entries:
+        // the words with trials are listed first, then 32 lanes per listed
+        // word place its set bits (rank = popcount below the bit), so a busy
+        // word costs no more than a quiet one
         {
-            int oc = off & 0xFFFF, oi = tot_c + (off >> 16);
+            int oc = off & 0xFFFF, oi = off >> 16, k = pre_w;
 #pragma unroll
             for (int i = 0; i < WPT; ++i) {
-                const int w = tid + i * NT;
-                uint32_t m = mc[i];
-                while (m) {
-                    const int bit = __ffs(m) - 1;
-                    m &= m - 1;
-                    sL[oc++] = (uint16_t)(w * 32 + bit);
-                }
-                m = mi[i];
-                while (m) {
-                    const int bit = __ffs(m) - 1;
-                    m &= m - 1;
-                    sL[oi++] = (uint16_t)(w * 32 + bit);
+                if (mc[i] | mi[i]) {
+                    sWL[k] = make_uint4((uint32_t)(tid + i * NT), mc[i], mi[i],
+                                        (uint32_t)oc | ((uint32_t)oi << 16));
+                    ++k;
+                    oc += __popc(mc[i]);
+                    oi += __popc(mi[i]);
                 }
             }
+        }
+        __syncthreads();
+        for (int x = tid; x < tot_w * 32; x += NT) {
+            const int b = x & 31;
+            const uint32_t bm = 1u << b;
+            const uint4 wl = sWL[x >> 5];
+            const uint16_t e = (uint16_t)(wl.x * 32 + b);
+            if (wl.y & bm) sL[(wl.w & 0xFFFFu) + __popc(wl.y & (bm - 1u))] = e;
+            else if (wl.z & bm) sL[tot_c + (wl.w >> 16) + __popc(wl.z & (bm - 1u))] = e;
         }
         __syncthreads();
 
@@ -415,30 +512,35 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             // every edge at the start of the run).  Each lane takes up to 4
             // trials per pass and issues all of their gathers before deciding.
             constexpr int R = 4;
-            const float4* q8v = reinterpret_cast<const float4*>(J.q8);
+            const FS_GLOBAL fs_f4* q8v = (const FS_GLOBAL fs_f4*)q8g;
+            // flat index of the region's top-left cell (may be negative; every
+            // listed cell lies inside the grid)
+            const int64_t jbase = (int64_t)r0 * J.W + (int64_t)w0 * 32;
             for (int k0 = 0; k0 < ntr; k0 += R * NT) {
                 int ent[R];
-                float4 qa[R], qb[R];
+                fs_f4 qa[R], qb[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
+                    if (k0 + r * NT >= ntr) break;   // uniform: no lane has trial r
                     const int k = k0 + r * NT + tid;
                     ent[r] = k < ntr ? (int)sL[k] : -1;
-                    qa[r] = qb[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    qa[r] = qb[r] = (fs_f4)(0.f);
                     if (k >= tot_c && k < ntr) {
                         const int w = ent[r] >> 5, bit = ent[r] & 31;
                         const int lr = w / RC, lc = w - (w / RC) * RC;
-                        const int64_t j = (int64_t)(r0 + lr) * J.W + ((w0 + lc) * 32 + bit);
+                        const int64_t j = jbase + (lr * J.W + lc * 32 + bit);
                         qa[r] = q8v[2 * j];
                         qb[r] = q8v[2 * j + 1];
                     }
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
+                    if (k0 + r * NT >= ntr) break;
                     const int k = k0 + r * NT + tid;
                     if (k >= ntr) continue;
                     const int w = ent[r] >> 5, bit = ent[r] & 31;
                     const int lr = w / RC, lc = w - (w / RC) * RC;
-                    const int64_t j = (int64_t)(r0 + lr) * J.W + ((w0 + lc) * 32 + bit);
+                    const int64_t j = jbase + (lr * J.W + lc * 32 + bit);
                     const bool interior = lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC;
                     uint32_t rw0, rw1;
                     philox_w01((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, scen,
@@ -447,29 +549,24 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                         if (u24(rw1) < J.p_continue) {
                             atomicOr(&sR[w], 1u << bit);
                         } else if (interior && J.tout) {
-                            J.tout[j] = t;
+                            gmem(J.tout)[j] = t;
                         }
                         if (interior) ++n_trials;
                         continue;
                     }
                     const float qs[8] = {qa[r].x, qa[r].y, qa[r].z, qa[r].w,
                                          qb[r].x, qb[r].y, qb[r].z, qb[r].w};
+                    const uint4 na = sN[w][0], nb = sN[w][1];
+                    const uint32_t nm[8] = {na.x, na.y, na.z, na.w, nb.x, nb.y, nb.z, nb.w};
                     float q[8];
 #pragma unroll
-                    for (int m = 0; m < 8; ++m) {
-                        int dr, dc;
-                        slot_dir(m, dr, dc);
-                        const int cl = lc * 32 + bit + dc;
-                        const bool burn = cl >= 0 && cl < RC * 32 &&
-                                          ((cB[(lr + dr) * RC + (cl >> 5)] >> (cl & 31)) & 1u);
-                        q[m] = burn ? qs[m] : 0.f;
-                    }
+                    for (int m = 0; m < 8; ++m) q[m] = ((nm[m] >> bit) & 1u) ? qs[m] : 0.f;
                     const float P = combine8(q);
                     const float u = u24(rw0);
                     if (u < P) {
                         atomicOr(&sR[w], 1u << bit);
-                        if (interior && J.yhat) J.yhat[j] = P;
-                        if (interior && J.tign) J.tign[j] = t;
+                        if (interior && J.yhat) gmem(J.yhat)[j] = P;
+                        if (interior && J.tign) gmem(J.tign)[j] = t;
                     }
                     if (interior) {
                         ++n_trials;
@@ -510,14 +607,14 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 return cl >= 0 && cl < RC * 32 &&
                        ((cB[(lr + dr) * RC + (cl >> 5)] >> (cl & 31)) & 1u);
             };
-            const float4 rec = J.rec[j];
+            const float4 rec = load_f4(J.rec, j);
             float P;
             float gl[4] = {0.f, 0.f, 0.f, 0.f};
             if (wide) {
                 int dr, dc;
                 slot_dir(e, dr, dc);
                 const bool burn = burning(dr, dc);
-                const float th = J.th8[j * 8 + e];
+                const float th = gmem(J.th8)[j * 8 + e];
                 Edge ed{0.f, 0.f, 0.f, 0.f, 0.f};
                 if (burn) ed = edge_terms(J, rec, th, dr, dc);
                 P = combine8_lanes(ed.q);
@@ -620,7 +717,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             for (int m = 0; m < 4; ++m) {
                 double acc = 0.0;
                 for (int v = 0; v < NWAVE; ++v) acc += sG[v * 4 + m];
-                J.gpart[(int64_t)g * 4 + m] += acc;
+                gmem(J.gpart)[(int64_t)g * 4 + m] += acc;
             }
         }
     }
@@ -810,6 +907,26 @@ k_overlap(DevScen J, int32_t parity, const uint8_t* __restrict__ target,
         if (in) atomicAdd((unsigned long long*)&out[0], (unsigned long long)in);
         if (un) atomicAdd((unsigned long long*)&out[1], (unsigned long long)un);
     }
+}
+
+// Probability of arrival over an ensemble of runs (Sec. 1): per cell, the
+// number of scenarios s0 .. s0+n-1 (one grid shape) in which the cell is
+// affected, added to counts.
+__global__ void __launch_bounds__(256)
+k_arrival(const DevScen* __restrict__ jobs, int32_t s0, int32_t n, int32_t parity,
+          uint32_t* __restrict__ counts) {
+    const DevScen& J0 = jobs[s0];
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= J0.W) return;
+    const int64_t o = (int64_t)r * J0.pitch + (c >> 5);
+    const int64_t PW = (int64_t)J0.H * J0.pitch;
+    uint32_t k = 0;
+    for (int s = s0; s < s0 + n; ++s) {
+        const uint32_t* B = jobs[s].planes[parity];
+        k += ((B[o] | B[PW + o]) >> (c & 31)) & 1u;
+    }
+    counts[(int64_t)r * J0.W + c] += k;
 }
 
 // ------------------------------------------------------------- prologue
@@ -1312,6 +1429,13 @@ hipError_t launch_overlap(hipStream_t st, const DevScen& J, int32_t parity, cons
     hipError_t e = launch_fill_u32(st, reinterpret_cast<uint32_t*>(out), 4, 0u);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_overlap, cell_grid(J.H, J.W), dim3(256), 0, st, J, parity, target, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_arrival(hipStream_t st, const DevScen* d_jobs, const DevScen& J0, int32_t s0,
+                          int32_t n, int32_t parity, uint32_t* counts) {
+    hipLaunchKernelGGL(k_arrival, cell_grid(J0.H, J0.W), dim3(256), 0, st, d_jobs, s0, n, parity,
+                       counts);
     return hipGetLastError();
 }
 

@@ -257,7 +257,44 @@ class Sim:
         i, u = (int(x) for x in self.overlap(s, target).cpu())
         return 1.0 if u == 0 else i / u
 
+    def arrival(self, s0: int = 0, n: Optional[int] = None, counts=None) -> torch.Tensor:
+        """Add, per cell, the number of scenarios s0 .. s0+n-1 (one grid shape)
+        in which the cell is affected to ``counts`` (uint32-compatible int32
+        H x W device tensor, created zeroed when None) and return it."""
+        n = self.n - s0 if n is None else int(n)
+        if not 0 <= s0 < self.n:
+            raise ValueError("s0 out of range")
+        H, W = self.shapes[s0]
+        if counts is None:
+            counts = torch.zeros((H, W), dtype=torch.int32, device=self.device)
+        if counts.dtype != torch.int32 or counts.numel() != H * W or not counts.is_contiguous():
+            raise ValueError("counts must be a contiguous int32 tensor of H*W cells")
+        self._check(self._lib.sim_arrival(self._h, int(s0), n, _ptr(counts)))
+        return counts
+
     def stats(self) -> dict:
         v = (ctypes.c_uint64 * 4)()
         self._check(self._lib.sim_stats(self._h, v))
         return dict(tiles=int(v[0]), trials=int(v[1]), ties=int(v[2]), launches=int(v[3]))
+
+
+def ensemble_arrival(scenario, seeds: Sequence[int], T: int, *, batch: Optional[int] = None,
+                     exec: Optional[dict] = None) -> torch.Tensor:
+    """Probability of arrival (Sec. 1): the fraction of runs, one per seed, in
+    which each cell is affected after T steps.  Runs go in batches of
+    ``batch`` scenarios (all of them at once by default) through one handle
+    per batch; returns an FP32 H x W device tensor."""
+    import dataclasses
+
+    seeds = [int(x) for x in seeds]
+    if not seeds:
+        raise ValueError("need at least one seed")
+    batch = len(seeds) if batch is None else max(1, int(batch))
+    counts = None
+    for b0 in range(0, len(seeds), batch):
+        part = [dataclasses.replace(scenario, seed=sd) for sd in seeds[b0:b0 + batch]]
+        sim = Sim(part, exec=exec)
+        sim.run(int(T))
+        counts = sim.arrival(0, len(part), counts)
+        del sim
+    return counts.to(torch.float32) / float(len(seeds))

@@ -555,3 +555,35 @@ def test_calibrate_sequence_mechanics(Sim):
             assert 0.2 <= th[0] <= 1.0 and np.all(th[1:] >= 0) and np.all(th <= 1)
         runs.append(theta.cpu().numpy())
     assert np.array_equal(runs[0], runs[1])
+
+
+# ------------------------------------------- ensemble probability of arrival
+
+def test_ensemble_arrival_matches_oracle(Sim):
+    """Sec. 1: the arrival map is the per-cell fraction of runs (one per
+    seed) that reach the cell; each run must be the oracle's run."""
+    from paper_2502_18738_amd.sim import ensemble_arrival
+    s = synth.make_lakes(72, 90, 68, T=40)
+    seeds = [11, 12, 13, 14, 15]
+    T = 40
+    want = np.zeros((s.H, s.W))
+    allowed = np.zeros((s.H, s.W), bool)
+    for sd in seeds:
+        sc = dataclasses.replace(s, seed=sd)
+        states, ties = oracle_traj(sc, T)
+        want += states[T] != 0
+        for t in range(1, T + 1):
+            if ties[t].any():
+                allowed |= maximum_filter(ties[t].astype(np.uint8), size=2 * (T - t) + 1) > 0
+    got = ensemble_arrival(s, seeds, T, batch=2).cpu().numpy().astype(np.float64) * len(seeds)
+    assert np.all(np.abs(got - np.round(got)) < 1e-4)
+    got = np.round(got)
+    assert np.array_equal(got[~allowed], want[~allowed])
+    # counts from one handle equal the sum of its scenarios' states
+    sim = Sim([dataclasses.replace(s, seed=sd) for sd in seeds])
+    sim.run(T)
+    c = sim.arrival(1, 3).cpu().numpy()
+    ref = sum((gstate(sim, b) != 0).astype(np.int64) for b in (1, 2, 3))
+    assert np.array_equal(c, ref)
+    with pytest.raises(Exception):
+        sim.arrival(3, 3)
