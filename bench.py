@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # state, F = (1+p_veg)(1+p_den), elevation, wind speed and direction, and
 # writes 2 bits): 0.5 + 4 + 4 + 8.
 DENSE_BYTES_PER_CELL_STEP = 16.5
-DEFAULT_EXEC = dict(tile_rows=16, tile_words=2, depth=16, skip=True)
+DEFAULT_EXEC = dict(tile_rows=32, tile_words=2, depth=32, skip=True)
 PLAIN_EXEC = dict(tile_rows=16, tile_words=8, depth=1, skip=False)
 
 
@@ -219,7 +219,7 @@ def leg_calib(args, torch, Sim, synth):
     # handle over the same scenarios at mid-run, then use its choice
     tune = Sim(true_s)
     tune.run(100)
-    cex = tune.autotune(16)
+    cex = tune.autotune(ck)   # one checkpoint segment: the launch pattern of a calibration run
     del tune
     sim = Sim(true_s, calib=True, T_max=T, ckpt_every=ck, exec=cex)
     theta = torch.tensor(start, dtype=torch.float32, device="cuda", requires_grad=True)
@@ -266,7 +266,7 @@ def leg_batched(args, torch, Sim, synth):
     scs = [synth.config3_scenario(b, T=T) for b in range(n)]
     sim = Sim(scs)
     sim.run(150)
-    ex = sim.autotune(16)
+    ex = sim.autotune(64)
     sim.reset()
 
     def run():

@@ -112,7 +112,7 @@ typedef struct {
 } sim_desc;
 
 /* Execution shape: rows x words of one tile (a word is 32 cells), steps per
- * launch (temporal block depth, 1 <= depth <= tile_rows and <= 16), and how
+ * launch (temporal block depth, 1 <= depth <= tile_rows and <= 32), and how
  * tiles with no burning cell within reach are skipped: 0 = every tile is
  * processed, 1 = a device-built worklist (tiles that burn mark their
  * neighbours for the next launch; a grid of resident work-groups walks it),
@@ -139,7 +139,7 @@ SIM_API int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* w
              size_t ws_bytes, void* stream, uint32_t flags, int32_t ckpt_every,
              int32_t T_max);
 
-/* Choose the execution shape (default: 16 rows x 2 words, depth 16, worklist skipping;
+/* Choose the execution shape (default: 32 rows x 2 words, depth 32, worklist skipping;
  * sim_autotune picks one by timing).  Only whitelisted shapes are compiled; others give
  * SIM_E_SHAPE. */
 SIM_API int sim_set_exec(sim_handle* h, const sim_exec* e);

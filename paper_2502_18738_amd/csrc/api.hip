@@ -32,15 +32,16 @@ struct ScenLayout {
     int32_t pitch;
     int64_t PW;          // words per bit-plane
     int64_t max_tiles;   // flag capacity
-    size_t rec, th8, q8, fuel, planes[2], flags[2], yhat, ckpt, tune, tign, tout;
+    size_t rec, th8, q8, g8, fuel, planes[2], flags[2], yhat, ckpt, tune, tign, tout;
 };
 
 struct Layout {
     size_t err, stats, box, part, jobs, tile_job, adj_jobs, adj_tile_job, gpart, ranges, lam,
-        cell0, bl0, gpart_tmap, masks, adj_masks, total;
+        cell0, bl0, ib0, gpart_tmap, masks, adj_masks, total;
     int32_t mask_words, adj_mask_words;
     int64_t total_cells;
     int32_t tmap_blocks;
+    int32_t max_h;
     std::vector<ScenLayout> s;
     std::vector<size_t> adj_planes[2], adj_flags[2];  // per (s, seg)
     int nseg;
@@ -62,9 +63,11 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
     L->stats = take(4 * sizeof(unsigned long long));
     L->box = take(4 * sizeof(int) * (size_t)n);
     for (int i = 0; i < n; ++i) max_h = std::max<int64_t>(max_h, d[i].H);
-    L->part = take(2 * sizeof(double) * (size_t)cdiv(max_h, 4));
+    L->max_h = (int32_t)max_h;
+    L->part = take(2 * sizeof(double) * (size_t)n * (size_t)cdiv(max_h, 4));
     L->jobs = take(sizeof(fs::DevScen) * (size_t)n);
     L->cell0 = take(sizeof(int64_t) * (size_t)(n + 1));
+    L->ib0 = take(sizeof(int32_t) * (size_t)(n + 1));
     L->total_cells = 0;
     for (int i = 0; i < n; ++i) L->total_cells += (int64_t)d[i].H * d[i].W;
     int64_t tiles = 0;
@@ -90,10 +93,11 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         s.planes[1] = take(8 * (size_t)s.PW);
         s.flags[0] = take((size_t)s.max_tiles);
         s.flags[1] = take((size_t)s.max_tiles);
-        s.yhat = s.ckpt = s.tune = s.tign = s.tout = 0;
+        s.yhat = s.ckpt = s.tune = s.tign = s.tout = s.g8 = 0;
         if (!calib) s.tune = take(8 * (size_t)s.PW);   // state saved while autotuning
         if (calib) {
             s.yhat = take(4 * (size_t)cells);
+            s.g8 = take(32 * (size_t)cells);
             s.tign = take(4 * (size_t)cells);
             s.tout = take(4 * (size_t)cells);
             s.ckpt = take(8 * (size_t)s.PW * (size_t)L->nseg);
@@ -224,6 +228,7 @@ struct sim_handle {
     int adj_method = 0;             // 0: checkpoint recompute, 1: time maps
     fs::Rings rings{-1, 0, 0, 0};   // step-ring attach set (first < 0: every step)
     std::vector<int32_t> bl0;
+    std::vector<int32_t> ib0;       // blocks of the state-reset kernel per scenario (prefix)
     std::vector<int64_t> cell0;
     hipStream_t cap = nullptr;      // private stream used only for capture
 
@@ -262,7 +267,7 @@ namespace {
 
 fs::TileShape shape_of(const sim_exec& e) {
     int km = 1;
-    for (int k : {1, 4, 8, 16})
+    for (int k : {1, 4, 8, 16, 32})
         if (k >= e.depth) { km = k; break; }
     return fs::TileShape{e.tile_rows, e.tile_words, km};
 }
@@ -322,13 +327,11 @@ int reset_state(sim_handle* h) {
     h->parity = 0;
     h->step = 0;
     h->q_dirty = true;   // every run from a reset rebuilds the propagation table
-    for (int i = 0; i < h->n; ++i) {
-        const fs::DevScen& J = h->job[i];
-        int rc = h->hip(fs::launch_init_state(h->st, J, h->d[i].f.init_burning, J.planes[0],
-                                              J.yhat, J.tign, J.tout), "init state");
-        if (rc) return rc;
-    }
-    int rc = refresh_worklist(h, false);   // init_state wrote both buffers
+    int rc = h->hip(fs::launch_init_state(h->st, h->d_jobs(),
+                                          reinterpret_cast<const int32_t*>(h->ws + h->L.ib0),
+                                          h->n, h->ib0.back()), "init state");
+    if (rc) return rc;
+    rc = refresh_worklist(h, false);   // init_state wrote both buffers
     if (rc) return rc;
     rc = h->hip(hipMemsetAsync(h->d_stats(), 0, 4 * sizeof(unsigned long long), h->st),
                 "clear stats");
@@ -403,7 +406,7 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
     // default execution shape
     int32_t max_pitch = 0;
     for (const auto& s : h->L.s) max_pitch = std::max(max_pitch, s.pitch);
-    h->ex = sim_exec{16, 2, 16, 1};
+    h->ex = sim_exec{32, 2, 32, 1};
     (void)max_pitch;
     h->sh = shape_of(h->ex);
 
@@ -433,6 +436,8 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
         J.rec = reinterpret_cast<const float4*>(h->ws + s.rec);
         J.th8 = reinterpret_cast<const float*>(h->ws + s.th8);
         J.q8 = reinterpret_cast<float*>(h->ws + s.q8);
+        J.ign = d.f.init_burning;
+        J.g8 = h->calib() ? reinterpret_cast<float*>(h->ws + s.g8) : nullptr;
         J.fuel = reinterpret_cast<const uint32_t*>(h->ws + s.fuel);
         J.planes[0] = reinterpret_cast<uint32_t*>(h->ws + s.planes[0]);
         J.planes[1] = reinterpret_cast<uint32_t*>(h->ws + s.planes[1]);
@@ -467,6 +472,11 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
     if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.cell0, h->cell0.data(),
                                         sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, h->st),
                          "upload cell offsets");
+    h->ib0.assign(1, 0);
+    for (int i = 0; i < n; ++i)
+        h->ib0.push_back(h->ib0.back() + descs[i].H * (int32_t)cdiv(32 * h->job[i].pitch, 256));
+    if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.ib0, h->ib0.data(), sizeof(int32_t) * (n + 1),
+                                        hipMemcpyHostToDevice, h->st), "upload reset blocks");
     if (!rc && h->calib()) {
         h->bl0.assign(1, 0);
         for (int i = 0; i < n; ++i)
@@ -506,7 +516,7 @@ int sim_set_exec(sim_handle* h, const sim_exec* e) {
     if (e->depth < 1 || e->depth > 32 || e->depth > e->tile_rows)
         return h->fail(SIM_E_SHAPE, "depth must be in [1, min(32, tile_rows)]");
     const fs::TileShape sh = shape_of(*e);
-    if (e->depth > 16 || !fs::step_shape_supported(sh, false) ||
+    if (!fs::step_shape_supported(sh, false) ||
         (h->calib() && !fs::step_shape_supported(sh, true)))
         return h->fail(SIM_E_SHAPE, "tile %dx%d words with depth %d is not compiled in",
                        e->tile_rows, e->tile_words, e->depth);
@@ -896,6 +906,8 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
                       "zero gradient");
     fs::Rings rg = h->rings;
     rg.T = T;
+    // both adjoints read the q8 / g8 tables of the current parameters
+    if (int rc = ensure_qtable(h)) return rc;
     if (h->adj_method == 1) {
         auto* gp = reinterpret_cast<double*>(h->ws + h->L.gpart_tmap);
         int rc = h->hip(fs::launch_adjoint_tmap(h->st, h->d_jobs(),
@@ -976,16 +988,13 @@ int sim_loss_grad(sim_handle* h, const uint8_t* target, int32_t kind, double* lo
     if (kind < SIM_LOSS_BCE || kind > SIM_LOSS_MSE) return h->fail(SIM_E_ARG, "bad loss kind");
     if (!h->calib()) return h->fail(SIM_E_STATE, "sim_loss_grad needs SIM_F_CALIB");
     float* lam = reinterpret_cast<float*>(h->ws + h->L.lam);
-    int64_t off = 0;
-    for (int i = 0; i < h->n; ++i) {
-        const fs::DevScen& J = h->job[i];
-        int rc = h->hip(fs::launch_loss(h->st, J.H, J.W, J.yhat, target + off, kind, lam + off,
-                                        reinterpret_cast<int*>(h->ws + h->L.box) + 4 * i,
-                                        reinterpret_cast<double*>(h->ws + h->L.part), loss + i),
-                        "loss");
-        if (rc) return rc;
-        off += (int64_t)J.H * J.W;
-    }
+    int rc = h->hip(fs::launch_loss(h->st, h->d_jobs(),
+                                    reinterpret_cast<const int64_t*>(h->ws + h->L.cell0), h->n,
+                                    h->L.max_h, target, kind, lam,
+                                    reinterpret_cast<int*>(h->ws + h->L.box),
+                                    reinterpret_cast<double*>(h->ws + h->L.part), loss),
+                    "loss");
+    if (rc) return rc;
     return adjoint(h, lam, grad);
 }
 

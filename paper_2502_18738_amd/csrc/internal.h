@@ -10,6 +10,9 @@
 //           neighbour slot into the cell for the current parameters (Eq. 2-5),
 //           rebuilt at the start of a run whenever parameters or the run
 //           changed.  Slot order: (dr, dc) row by row, centre skipped.
+//   g8      8 floats per cell (calibration handles only): F e^z of each edge,
+//           i.e. d x / d p_h of Eq. 2, written with q8; the adjoints build the
+//           remaining derivatives from it without transcendental functions.
 //   fuel    one bit per cell (F > 0), rows of `pitch` 32-bit words.
 //   planes  two ping-pong buffers; each holds the burning bit-plane followed
 //           by the burned bit-plane (2 * H * pitch words): 2 bits per cell.
@@ -39,6 +42,8 @@ struct DevScen {
     const float4* rec;         // per-cell record
     const float* th8;          // slope (Eq. 1, degrees) toward each of the 8 neighbours
     float* q8;                 // f_p(p_propagate) of each of the 8 incoming edges (per run)
+    float* g8;                 // F e^z of each incoming edge (calibration) or nullptr
+    const uint8_t* ign;        // caller's initial burning cells (H*W, non-zero = burning)
     const uint32_t* fuel;      // fuel bit-plane
     uint32_t* planes[2];       // ping-pong state buffers
     uint8_t* flags[2];         // per-tile flags, per parity
@@ -101,8 +106,11 @@ hipError_t launch_overlap(hipStream_t st, const DevScen& job, int32_t parity, co
 // d_cell0: n + 1 prefix sums of cell counts (block ranges per scenario).
 hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
                          int64_t total_cells);
-hipError_t launch_init_state(hipStream_t st, const DevScen& job, const uint8_t* ign,
-                             uint32_t* planes, float* yhat, int32_t* tign, int32_t* tout);
+// State of every scenario back to its initial burning cells (both ping-pong
+// buffers, accumulator, time maps); d_ib0 = n + 1 prefix sums of the blocks
+// per scenario, H * ceil(32 pitch / 256).
+hipError_t launch_init_state(hipStream_t st, const DevScen* d_jobs, const int32_t* d_ib0,
+                             int32_t n, int32_t nblocks);
 // Time-map adjoint: one pass over every cell of every scenario; bl0 = n + 1
 // prefix sums of ceil(cells / 256) per scenario; writes gpart[block][4].
 hipError_t launch_adjoint_tmap(hipStream_t st, const DevScen* d_jobs, const int32_t* d_bl0,
@@ -148,10 +156,12 @@ struct SeedBlock {
 hipError_t launch_set_seeds(hipStream_t st, DevScen* d_jobs, const SeedBlock& sb);
 hipError_t launch_pignite(hipStream_t st, const DevScen* d_job, const DevScen& job,
                           int32_t parity, float* out);
-// Eq. 10 for one H x W scenario: writes lambda = dL/dyhat and *loss_out.
-// d_box holds 4 ints, d_part 2 * ceil(H / 4) doubles.
-hipError_t launch_loss(hipStream_t st, int32_t H, int32_t W, const float* yhat,
-                       const uint8_t* y, int32_t kind, float* lambda, int* d_box,
+// Eq. 10 for each of the n scenarios (accumulators from their descriptors;
+// y and lambda concatenated, scenario i at d_cell0[i]): writes lambda =
+// dL/dyhat and loss_out[i].  d_box holds 4 n ints, d_part
+// 2 n ceil(max_h / 4) doubles.
+hipError_t launch_loss(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
+                       int32_t max_h, const uint8_t* y, int32_t kind, float* lambda, int* d_box,
                        double* d_part, double* loss_out);
 // grad[s] = sum of gpart[g] over tiles g in [ranges[s], ranges[s+1]).
 hipError_t launch_grad_reduce(hipStream_t st, const double* gpart, const int32_t* d_ranges,

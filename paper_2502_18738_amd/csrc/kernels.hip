@@ -116,18 +116,9 @@ __device__ __forceinline__ float por(float a, float b) { return a + b * (1.f - a
 
 // Eq. 9 over the 8 neighbour slots with a fixed pairing tree
 // ((0,1),(2,3)),((4,5),(6,7)).  Every kernel that evaluates p_ignite uses this
-// tree (sequentially here, across 8 lanes in combine8_lanes), so all of them
-// produce bit-identical values.
+// tree, so all of them produce bit-identical values.
 __device__ __forceinline__ float combine8(const float q[8]) {
     return por(por(por(q[0], q[1]), por(q[2], q[3])), por(por(q[4], q[5]), por(q[6], q[7])));
-}
-
-// The same tree across an aligned group of 8 lanes holding q of slots 0..7;
-// the result is valid in the group's first lane.
-__device__ __forceinline__ float combine8_lanes(float q) {
-    const float a = por(q, __shfl_xor(q, 1, 64));
-    const float b = por(a, __shfl_xor(a, 2, 64));
-    return por(b, __shfl_xor(b, 4, 64));
 }
 
 // p_ignite of cell j from its 8 slots, one lane; nb(dr, dc) says whether that
@@ -157,48 +148,6 @@ __device__ __forceinline__ bool attached(const Rings& rg, int t) {
     return false;
 }
 
-// p_ignite (Eq. 9, the fixed tree) of cell j and its derivatives with respect
-// to (p_h, a, c1, c2) for the burning-neighbour slots nb(dr, dc), one lane:
-// dP/dq_m = prod over the other slots of (1 - q) (prefix x suffix products, so
-// a saturated q = 1 never divides), dq/dx = c (1 - q^2) and
-// dx/d(p_h, a, c1, c2) = (F e^z, x theta_s, x V, x V (cos - 1)).
-template <class NB>
-__device__ __forceinline__ float pignite_grad(const DevScen& J, int64_t j, NB nb, float gl[4]) {
-    const float4 rec = load_f4(J.rec, j);
-    const FS_GLOBAL float* th8 = gmem(J.th8);
-    float q[8], dx[8][4];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        int dr, dc;
-        slot_dir(m, dr, dc);
-        q[m] = 0.f;
-        dx[m][0] = dx[m][1] = dx[m][2] = dx[m][3] = 0.f;
-        if (nb(dr, dc)) {
-            const Edge ed = edge_terms(J, rec, th8[j * 8 + m], dr, dc);
-            q[m] = ed.q;
-            dx[m][0] = rec.x * ed.ez;
-            dx[m][1] = ed.x * ed.th;
-            dx[m][2] = ed.x * rec.y;
-            dx[m][3] = ed.x * ed.vterm;
-        }
-    }
-    const float P = combine8(q);
-    float pre[8], suf[8], acc = 1.f;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) { pre[m] = acc; acc = acc * (1.f - q[m]); }
-    acc = 1.f;
-#pragma unroll
-    for (int m = 7; m >= 0; --m) { suf[m] = acc; acc = acc * (1.f - q[m]); }
-    gl[0] = gl[1] = gl[2] = gl[3] = 0.f;
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const float sc = pre[m] * suf[m] * (J.c * (1.f - q[m] * q[m]));
-#pragma unroll
-        for (int d = 0; d < 4; ++d) gl[d] = gl[d] + sc * dx[m][d];
-    }
-    return P;
-}
-
 // Inclusive prefix sum over the 64 lanes of a wavefront with DPP lane moves
 // (shifts inside 16-lane rows, then the row-15 and row-31 broadcasts), so the
 // scan costs six register-to-register moves instead of LDS permutes.  Every
@@ -211,6 +160,44 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
     x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15
     x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return x;
+}
+
+// d p_ignite / d(p_h, a, c1, c2) of cell j from tables: sm has bit m set for
+// each burning neighbour slot, q[m] its Eq. 5 value (0 for other slots, as
+// gathered from q8).  With dP/dq_m = prod over the other slots of (1 - q)
+// (prefix x suffix products), dq/dx = c (1 - q^2), dx/dp_h = F e^z (g8),
+// x = p_h F e^z and dx/d(a, c1, c2) = x (theta_s, V, V (cos - 1)).  No
+// transcendental function is evaluated; both adjoints call this routine, so
+// they agree cell by cell.
+// The table rows of cell j (rec, g8 and th8 entries) are passed in, so that a
+// caller can issue their reads early.
+__device__ __forceinline__ void pignite_grad_tab(const DevScen& J, float4 rec, fs_f4 ga, fs_f4 gb,
+                                                 fs_f4 ta, fs_f4 tb, uint32_t sm,
+                                                 const float q[8], float gl[4]) {
+    const float gv[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+    const float th[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
+    float pre[8], suf[8], acc = 1.f;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) { pre[m] = acc; acc = acc * (1.f - q[m]); }
+    acc = 1.f;
+#pragma unroll
+    for (int m = 7; m >= 0; --m) { suf[m] = acc; acc = acc * (1.f - q[m]); }
+    gl[0] = gl[1] = gl[2] = gl[3] = 0.f;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        if (!((sm >> m) & 1u)) continue;
+        int dr, dc;
+        slot_dir(m, dr, dc);
+        float proj = (float)(-dc) * rec.z + (float)dr * rec.w;
+        if (dr != 0 && dc != 0) proj = proj * kSqrtHalf;
+        const float vterm = proj - rec.y;
+        const float x = J.p_h * gv[m];
+        const float sc = pre[m] * suf[m] * (J.c * (1.f - q[m] * q[m]));
+        gl[0] = gl[0] + sc * gv[m];
+        gl[1] = gl[1] + sc * (x * th[m]);
+        gl[2] = gl[2] + sc * (x * rec.y);
+        gl[3] = gl[3] + sc * (x * vterm);
+    }
 }
 
 template <int NWAVE>
@@ -288,14 +275,17 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     static_assert(NW * 32 < 65536, "trial list entries are 16-bit");
     static_assert(KM <= TR && KM <= 32, "halo deeper than a tile");
 
-    __shared__ uint32_t sB[2][NW], sD[2][NW], sU[NW], sR[NW];
+    // burning plane ping-pong: sB[cur] = S(t-1), sB[cur ^ 1] collects the
+    // successful trials of step t, which are exactly the burning cells of S(t).
+    // The burned plane of a word lives in its owner thread's registers.
+    __shared__ uint32_t sB[2][NW], sU[NW];
     __shared__ uint16_t sL[LCAP];
     // words holding a trial this step: (word index, continue mask, ignition
     // mask, offsets of their first list entries: continue | ignition << 16)
     __shared__ uint4 sWL[NW];
-    // forward: per word, which of the 8 neighbour slots of each of its 32
-    // cells burn (one mask per slot), written for words with ignition trials
-    __shared__ uint4 sN[ADJ ? 1 : NW][2];
+    // per word, which of the 8 neighbour slots of each of its 32 cells burn
+    // (one mask per slot), written for words with ignition trials
+    __shared__ uint4 sN[NW][2];
     __shared__ int sWave[2 * NWAVE];
     __shared__ int sFlag;
     __shared__ double sG[ADJ ? NWAVE * 4 : 1];
@@ -390,10 +380,12 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     const int r0 = trow * TR - KM;
     const int w0 = tcol * TC - 1;
     uint32_t origB[WPT], origD[WPT];
+    uint32_t dreg[WPT], bprev[WPT];   // burned plane; burning plane one step back
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
         const int w = tid + i * NT;
         origB[i] = origD[i] = 0;
+        dreg[i] = bprev[i] = 0;
         if (w < NW) {
             const int lr = w / RC, lc = w - (w / RC) * RC;
             const int gr = r0 + lr, gw = w0 + lc;
@@ -405,13 +397,17 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 u = fuel[o];
             }
             sB[0][w] = b;
-            sD[0][w] = d;
             sU[w] = u;
             origB[i] = b;
             origD[i] = d;
         }
     }
     if (tid == 0) sFlag = 0;
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+        dreg[i] = origD[i];
+        bprev[i] = origB[i];
+    }
 
     const uint32_t k0s = J.seed_lo, k1s = J.seed_hi, scen = J.scen_id;
     double gsum[4] = {0.0, 0.0, 0.0, 0.0};
@@ -423,7 +419,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         const int t = J.t_base + t_off + s;
         const int lo = s, hi = RR - s;
         const uint32_t* cB = sB[cur];
-        const uint32_t* cD = sD[cur];
+        uint32_t* nR = sB[cur ^ 1];
 
         // trial masks of this thread's words: continue trials (burning cells)
         // and ignition trials (burnable cells with fuel and a burning neighbour)
@@ -458,17 +454,17 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     const uint32_t n5 = (dn << 1) | (dnL >> 31), n6 = dn,
                                    n7 = (dn >> 1) | (dnR << 31);
                     const uint32_t nbm = n0 | n1 | n2 | n3 | n4 | n5 | n6 | n7;
-                    const uint32_t dw = cD[w];
+                    // burned at t-1: burned before, or burning at t-2 and not at t-1
+                    dreg[i] |= bprev[i] & ~mid;
+                    bprev[i] = mid;
                     mc[i] = mid;
-                    mi[i] = nbm & ~mid & ~dw & sU[w];
+                    mi[i] = nbm & ~mid & ~dreg[i] & sU[w];
                     cnt += __popc(mc[i]) | (__popc(mi[i]) << 16);
                     nne += (mc[i] | mi[i]) != 0u;
-                    sR[w] = 0;
-                    if constexpr (!ADJ) {
-                        if (mi[i]) {
-                            sN[w][0] = make_uint4(n0, n1, n2, n3);
-                            sN[w][1] = make_uint4(n4, n5, n6, n7);
-                        }
+                    nR[w] = 0;
+                    if (mi[i]) {
+                        sN[w][0] = make_uint4(n0, n1, n2, n3);
+                        sN[w][1] = make_uint4(n4, n5, n6, n7);
                     }
                 }
             }
@@ -506,31 +502,58 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         __syncthreads();
 
         const int ntr = tot_c + tot_i;
-        if constexpr (!ADJ) {
-            // Forward: p_ignite of an ignition trial is Eq. 9 over the q8 entries
-            // of its burning neighbour slots (the Eq. 2-5 work was done for
-            // every edge at the start of the run).  Each lane takes up to 4
-            // trials per pass and issues all of their gathers before deciding.
-            constexpr int R = 4;
+        {
+            // p_ignite of an ignition trial is Eq. 9 over the q8 entries of its
+            // burning neighbour slots (the Eq. 2-5 work was done for every edge
+            // at the start of the run).  Each lane takes up to 4 trials per pass
+            // and issues all of their gathers before deciding.  The adjoint
+            // recompute takes the same decisions from the same values and, for
+            // the cells that ignite inside the tile at an attached step, adds
+            // lambda_j * d p_ignite_j / d theta (Eq. 2-5 and 9 differentiated).
+            // the adjoint also reads each interior trial's gradient rows with its
+            // q8 row (one round trip per step), so it holds one trial per lane
+            // per pass (fewer registers, more resident waves; measured fastest)
+            constexpr int R = ADJ ? 1 : 4;
+            const bool att = ADJ && attached(rings, t);
             const FS_GLOBAL fs_f4* q8v = (const FS_GLOBAL fs_f4*)q8g;
+            const FS_GLOBAL fs_f4* g8v = (const FS_GLOBAL fs_f4*)gmem(J.g8);
+            const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
             // flat index of the region's top-left cell (may be negative; every
             // listed cell lies inside the grid)
             const int64_t jbase = (int64_t)r0 * J.W + (int64_t)w0 * 32;
             for (int k0 = 0; k0 < ntr; k0 += R * NT) {
                 int ent[R];
                 fs_f4 qa[R], qb[R];
+                fs_f4 ga[R], gb[R], ta[R], tb[R];   // adjoint only
+                float4 rc[R];
+                float lj[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (k0 + r * NT >= ntr) break;   // uniform: no lane has trial r
                     const int k = k0 + r * NT + tid;
                     ent[r] = k < ntr ? (int)sL[k] : -1;
                     qa[r] = qb[r] = (fs_f4)(0.f);
+                    if constexpr (ADJ) {
+                        ga[r] = gb[r] = ta[r] = tb[r] = (fs_f4)(0.f);
+                        rc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        lj[r] = 0.f;
+                    }
                     if (k >= tot_c && k < ntr) {
                         const int w = ent[r] >> 5, bit = ent[r] & 31;
                         const int lr = w / RC, lc = w - (w / RC) * RC;
                         const int64_t j = jbase + (lr * J.W + lc * 32 + bit);
                         qa[r] = q8v[2 * j];
                         qb[r] = q8v[2 * j + 1];
+                        if constexpr (ADJ) {
+                            if (att && lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC) {
+                                ga[r] = g8v[2 * j];
+                                gb[r] = g8v[2 * j + 1];
+                                ta[r] = t8v[2 * j];
+                                tb[r] = t8v[2 * j + 1];
+                                rc[r] = load_f4(J.rec, j);
+                                lj[r] = lam[J.lam_off + j];
+                            }
+                        }
                     }
                 }
 #pragma unroll
@@ -547,7 +570,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                                k0s, k1s, rw0, rw1);
                     if (k < tot_c) {  // burning: continue trial
                         if (u24(rw1) < J.p_continue) {
-                            atomicOr(&sR[w], 1u << bit);
+                            atomicOr(&nR[w], 1u << bit);
                         } else if (interior && J.tout) {
                             gmem(J.tout)[j] = t;
                         }
@@ -564,9 +587,20 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     const float P = combine8(q);
                     const float u = u24(rw0);
                     if (u < P) {
-                        atomicOr(&sR[w], 1u << bit);
+                        atomicOr(&nR[w], 1u << bit);
                         if (interior && J.yhat) gmem(J.yhat)[j] = P;
                         if (interior && J.tign) gmem(J.tign)[j] = t;
+                        if constexpr (ADJ) {
+                            if (interior && att) {
+                                uint32_t sm = 0;   // burning slots
+#pragma unroll
+                                for (int m = 0; m < 8; ++m) sm |= ((nm[m] >> bit) & 1u) << m;
+                                float gl[4];
+                                pignite_grad_tab(J, rc[r], ga[r], gb[r], ta[r], tb[r], sm, q, gl);
+#pragma unroll
+                                for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj[r] * gl[m]);
+                            }
+                        }
                     }
                     if (interior) {
                         ++n_trials;
@@ -574,105 +608,8 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     }
                 }
             }
-        } else {
-        // Adjoint recompute: the same p_ignite (same Eq. 2-5 function on the
-        // same inputs, same Eq. 9 tree) plus its derivatives.  Continue trials
-        // take one lane each.  Ignition trials take an aligned group of 8 lanes
-        // (one per neighbour slot, the per-edge chains side by side) when all
-        // trials of the step fit in one pass; otherwise one lane each.
-        const bool wide = tot_c + 8 * tot_i <= NT;
-        const int base_i = wide ? ((tot_c + 7) & ~7) : tot_c;
-        const int nslots = base_i + (wide ? 8 : 1) * tot_i;
-        for (int k0 = 0; k0 < nslots; k0 += NT) {
-            const int k = k0 + tid;
-            if (k >= nslots) continue;
-            const bool cont = k < tot_c;
-            if (!cont && k < base_i) continue;   // padding before the 8-aligned groups
-            const int e = wide ? (k & 7) : 0;
-            const int ent = cont ? sL[k] : sL[tot_c + (wide ? (k - base_i) >> 3 : k - base_i)];
-            const int w = ent >> 5, bit = ent & 31;
-            const int lr = w / RC, lc = w - (w / RC) * RC;
-            const int64_t j = (int64_t)(r0 + lr) * J.W + ((w0 + lc) * 32 + bit);
-            const bool interior = lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC;
-            uint32_t rw0, rw1;
-            philox_w01((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, scen, k0s, k1s,
-                       rw0, rw1);
-            if (cont) {
-                if (u24(rw1) < J.p_continue) atomicOr(&sR[w], 1u << bit);
-                if (interior) ++n_trials;
-                continue;
-            }
-            auto burning = [&](int dr, int dc) -> bool {
-                const int cl = lc * 32 + bit + dc;
-                return cl >= 0 && cl < RC * 32 &&
-                       ((cB[(lr + dr) * RC + (cl >> 5)] >> (cl & 31)) & 1u);
-            };
-            const float4 rec = load_f4(J.rec, j);
-            float P;
-            float gl[4] = {0.f, 0.f, 0.f, 0.f};
-            if (wide) {
-                int dr, dc;
-                slot_dir(e, dr, dc);
-                const bool burn = burning(dr, dc);
-                const float th = gmem(J.th8)[j * 8 + e];
-                Edge ed{0.f, 0.f, 0.f, 0.f, 0.f};
-                if (burn) ed = edge_terms(J, rec, th, dr, dc);
-                P = combine8_lanes(ed.q);
-                // d p_ignite / d q_e = prod over the other slots of (1 - q)
-                const float om = 1.f - ed.q;
-                const int g0 = threadIdx.x & 56;
-                float prod = 1.f;
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    const float o = __shfl(om, g0 + m, 64);
-                    prod = prod * (m == e ? 1.f : o);
-                }
-                const float sc = prod * (J.c * (1.f - ed.q * ed.q));
-                gl[0] = sc * (rec.x * ed.ez);       // dx/dp_h = F e^z
-                gl[1] = sc * (ed.x * ed.th);        // dx/da   = x theta_s
-                gl[2] = sc * (ed.x * rec.y);        // dx/dc1  = x V
-                gl[3] = sc * (ed.x * ed.vterm);     // dx/dc2  = x V (cos - 1)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    gl[m] = gl[m] + __shfl_xor(gl[m], 1, 64);
-                    gl[m] = gl[m] + __shfl_xor(gl[m], 2, 64);
-                    gl[m] = gl[m] + __shfl_xor(gl[m], 4, 64);
-                }
-            } else {
-                P = pignite_grad(J, j, burning, gl);
-            }
-            if (e == 0) {
-                const float u = u24(rw0);
-                if (u < P) {
-                    atomicOr(&sR[w], 1u << bit);
-                    if (interior && attached(rings, t)) {
-                        const float lj = lam[J.lam_off + j];
-#pragma unroll
-                        for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj * gl[m]);
-                    }
-                }
-                if (interior) {
-                    ++n_trials;
-                    if (fabsf(u - P) <= kTieEps) ++n_ties;
-                }
-            }
         }
-        }
-        __syncthreads();
-
-        // combine: burning' = successful trials; burned' = burned | burnt out
-#pragma unroll
-        for (int i = 0; i < WPT; ++i) {
-            const int w = tid + i * NT;
-            if (w < NW) {
-                const int lr = w / RC;
-                if (lr >= lo && lr < hi) {
-                    const uint32_t bw = cB[w], r = sR[w];
-                    sB[cur ^ 1][w] = r;
-                    sD[cur ^ 1][w] = cD[w] | (bw & ~r);
-                }
-            }
-        }
+        // the next step's opening barrier completes this step's trials
         cur ^= 1;
     }
     __syncthreads();
@@ -688,7 +625,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 const int gr = r0 + lr, gw = w0 + lc;
                 if (gr < H && gw < pitch) {
                     const int64_t o = (int64_t)gr * pitch + gw;
-                    const uint32_t nb = sB[cur][w], nd = sD[cur][w];
+                    const uint32_t nb = sB[cur][w], nd = dreg[i] | (bprev[i] & ~nb);
                     pout[o] = nb;
                     pout[PW + o] = nd;
                     anyB |= nb != 0u;
@@ -809,16 +746,23 @@ k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, in
     const float4* tv = reinterpret_cast<const float4*>(J.th8 + j * 8);
     const float4 ta = tv[0], tb = tv[1];
     const float th[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
-    float q[8];
+    float q[8], g[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         int dr, dc;
         slot_dir(m, dr, dc);
-        q[m] = edge_terms(J, rec, th[m], dr, dc).q;
+        const Edge e = edge_terms(J, rec, th[m], dr, dc);
+        q[m] = e.q;
+        g[m] = rec.x * e.ez;
     }
     float4* o = reinterpret_cast<float4*>(J.q8 + j * 8);
     o[0] = make_float4(q[0], q[1], q[2], q[3]);
     o[1] = make_float4(q[4], q[5], q[6], q[7]);
+    if (J.g8) {
+        float4* og = reinterpret_cast<float4*>(J.g8 + j * 8);
+        og[0] = make_float4(g[0], g[1], g[2], g[3]);
+        og[1] = make_float4(g[4], g[5], g[6], g[7]);
+    }
 }
 
 // ------------------------------------------------ wind, spotting, metrics
@@ -981,11 +925,25 @@ k_prologue(int32_t H, int32_t W, int32_t pitch, const float* __restrict__ p_veg,
 }
 
 __global__ void __launch_bounds__(256)
-k_init_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ ign,
-             uint32_t* __restrict__ planes, uint32_t* __restrict__ planes2,
-             float* __restrict__ yhat, int32_t* __restrict__ tign, int32_t* __restrict__ tout) {
-    const int r = blockIdx.y;
-    const int c = blockIdx.x * 256 + threadIdx.x;
+k_init_state(const DevScen* __restrict__ jobs, const int32_t* __restrict__ ib0, int32_t n) {
+    const int b = blockIdx.x;
+    int lo = 0, hi = n;   // scenario s with ib0[s] <= b < ib0[s + 1]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (ib0[mid] <= b) lo = mid; else hi = mid;
+    }
+    const DevScen& J = jobs[lo];
+    const int H = J.H, W = J.W, pitch = J.pitch;
+    const uint8_t* ign = J.ign;
+    uint32_t* planes = J.planes[0];
+    uint32_t* planes2 = J.planes[1];
+    float* yhat = J.yhat;
+    int32_t* tign = J.tign;
+    int32_t* tout = J.tout;
+    const int bx = (pitch * 32 + 255) / 256;
+    const int local = b - ib0[lo];
+    const int r = local / bx;
+    const int c = (local - r * bx) * 256 + threadIdx.x;
     const int lane = threadIdx.x & 63;
     bool burning = false;
     if (c < W) {
@@ -996,7 +954,7 @@ k_init_state(int32_t H, int32_t W, int32_t pitch, const uint8_t* __restrict__ ig
         if (tout) tout[j] = INT_MAX;
     }
     const unsigned long long mb = __ballot(burning);
-    const int wbase = (blockIdx.x * 256 + (threadIdx.x & ~63)) >> 5;
+    const int wbase = ((local - r * bx) * 256 + (threadIdx.x & ~63)) >> 5;
     const int64_t PW = (int64_t)H * pitch;
     if (lane == 0 || lane == 32) {
         const int w = wbase + (lane >> 5);
@@ -1029,14 +987,28 @@ k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0
         const int tj = J.tign[j];
         if (tj >= 1 && tj <= rings.T && attached(rings, tj)) {
             const int r = (int)(j / J.W), c = (int)(j - (int64_t)r * J.W);
-            auto nb = [&](int dr, int dc) -> bool {
+            // burning neighbours at tj - 1: ignited by then and not yet out
+            uint32_t sm = 0;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                int dr, dc;
+                slot_dir(m, dr, dc);
                 const int rr = r + dr, cc = c + dc;
-                if (rr < 0 || rr >= J.H || cc < 0 || cc >= J.W) return false;
-                const int64_t i = (int64_t)rr * J.W + cc;
-                return J.tign[i] <= tj - 1 && tj - 1 < J.tout[i];
-            };
+                if (rr >= 0 && rr < J.H && cc >= 0 && cc < J.W) {
+                    const int64_t i = (int64_t)rr * J.W + cc;
+                    if (J.tign[i] <= tj - 1 && tj - 1 < J.tout[i]) sm |= 1u << m;
+                }
+            }
+            const float4 qa = load_f4(J.q8, 2 * j), qb = load_f4(J.q8, 2 * j + 1);
+            const float qv[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+            float q[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) q[m] = ((sm >> m) & 1u) ? qv[m] : 0.f;
+            const FS_GLOBAL fs_f4* g8v = (const FS_GLOBAL fs_f4*)gmem(J.g8);
+            const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
             float gl[4];
-            pignite_grad(J, j, nb, gl);
+            pignite_grad_tab(J, load_f4(J.rec, j), g8v[2 * j], g8v[2 * j + 1], t8v[2 * j],
+                             t8v[2 * j + 1], sm, q, gl);
             const float lj = lam[J.lam_off + j];
 #pragma unroll
             for (int m = 0; m < 4; ++m) g[m] = (double)(lj * gl[m]);
@@ -1166,24 +1138,50 @@ k_grad_reduce(const double* __restrict__ gpart, const int32_t* __restrict__ rang
 
 // --------------------------------------------------------------- Eq. 10
 
-// Bounding box of (yhat != 0) | (y != 0): box = {rmin, rmax, cmin, cmax}.
+// The loss kernels cover every scenario of a handle in one launch each:
+// scenario i = blockIdx.y (blockIdx.x for k_loss_final) reads its accumulator
+// from its descriptor and its target / writes its lambda at offset cell0[i] of
+// the concatenated arrays; box holds 4 ints and part 2 * maxparts doubles per
+// scenario.
+
+// Bounding box of (yhat != 0) | (y != 0): box = {rmin, rmax, cmin, cmax}.  A
+// block strides over rows, reduces its own box in LDS and merges it with four
+// atomics, so the atomics do not contend per cell.
 __global__ void __launch_bounds__(256)
-k_loss_box(int32_t H, int32_t W, const float* __restrict__ yhat, const uint8_t* __restrict__ y,
-           int* __restrict__ box) {
-    const int r = blockIdx.y;
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    bool nz = false;
-    if (c < W) {
-        const int64_t j = (int64_t)r * W + c;
-        nz = yhat[j] != 0.f || y[j] != 0;
+k_loss_box(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0,
+           const uint8_t* __restrict__ y_all, int* __restrict__ box_all) {
+    const DevScen& J = jobs[blockIdx.y];
+    const float* yhat = J.yhat;
+    const uint8_t* y = y_all + cell0[blockIdx.y];
+    int v[4] = {INT_MAX, -1, INT_MAX, -1};
+    for (int r = blockIdx.x; r < J.H; r += gridDim.x)
+        for (int c = threadIdx.x; c < J.W; c += 256) {
+            const int64_t j = (int64_t)r * J.W + c;
+            if (yhat[j] != 0.f || y[j] != 0) {
+                v[0] = min(v[0], r);
+                v[1] = max(v[1], r);
+                v[2] = min(v[2], c);
+                v[3] = max(v[3], c);
+            }
+        }
+    __shared__ int sh[4][256];
+    for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] = v[m];
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) {
+            sh[0][threadIdx.x] = min(sh[0][threadIdx.x], sh[0][threadIdx.x + d]);
+            sh[1][threadIdx.x] = max(sh[1][threadIdx.x], sh[1][threadIdx.x + d]);
+            sh[2][threadIdx.x] = min(sh[2][threadIdx.x], sh[2][threadIdx.x + d]);
+            sh[3][threadIdx.x] = max(sh[3][threadIdx.x], sh[3][threadIdx.x + d]);
+        }
+        __syncthreads();
     }
-    const unsigned long long m = __ballot(nz);
-    if ((threadIdx.x & 63) == 0 && m) {
-        const int cbase = blockIdx.x * 256 + (threadIdx.x & ~63);
-        atomicMin(&box[0], r);
-        atomicMax(&box[1], r);
-        atomicMin(&box[2], cbase + (__ffsll((long long)m) - 1));
-        atomicMax(&box[3], cbase + 63 - (__clzll((long long)m)));
+    if (threadIdx.x == 0 && sh[1][0] >= 0) {
+        int* box = box_all + 4 * blockIdx.y;
+        atomicMin(&box[0], sh[0][0]);
+        atomicMax(&box[1], sh[1][0]);
+        atomicMin(&box[2], sh[2][0]);
+        atomicMax(&box[3], sh[3][0]);
     }
 }
 
@@ -1191,10 +1189,18 @@ k_loss_box(int32_t H, int32_t W, const float* __restrict__ yhat, const uint8_t* 
 // 1/2).  Writes lambda = dL/dyhat and per-block FP64 partial sums
 // part[block] = (bce_sum, mse_sum); one block per 4 rows (a pool row).
 __global__ void __launch_bounds__(256)
-k_loss_terms(int32_t H, int32_t W, const float* __restrict__ yhat, const uint8_t* __restrict__ y,
-             int32_t kind, const int* __restrict__ box, float* __restrict__ lambda,
-             double* __restrict__ part) {
+k_loss_terms(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0,
+             const uint8_t* __restrict__ y_all, int32_t kind, const int* __restrict__ box_all,
+             float* __restrict__ lam_all, double* __restrict__ part_all, int32_t maxparts) {
+    const DevScen& J = jobs[blockIdx.y];
+    const int H = J.H, W = J.W;
     const int pr = blockIdx.x;  // rows 4 pr .. 4 pr + 3
+    if (4 * pr >= H) return;    // whole block: this scenario has fewer rows
+    const float* yhat = J.yhat;
+    const uint8_t* y = y_all + cell0[blockIdx.y];
+    float* lambda = lam_all + cell0[blockIdx.y];
+    const int* box = box_all + 4 * blockIdx.y;
+    double* part = part_all + 2 * (int64_t)blockIdx.y * maxparts;
     const int b0 = box[0], b1 = box[1], c0 = box[2], c1 = box[3];
     const bool has_box = b1 >= b0;
     const double N = has_box ? (double)(b1 - b0 + 1) * (double)(c1 - c0 + 1) : 1.0;
@@ -1251,8 +1257,14 @@ k_loss_terms(int32_t H, int32_t W, const float* __restrict__ yhat, const uint8_t
 }
 
 __global__ void __launch_bounds__(256)
-k_loss_final(int32_t H, int32_t W, int32_t kind, const int* __restrict__ box,
-             const double* __restrict__ part, int32_t nparts, double* __restrict__ loss) {
+k_loss_final(const DevScen* __restrict__ jobs, int32_t kind, const int* __restrict__ box_all,
+             const double* __restrict__ part_all, int32_t maxparts, double* __restrict__ loss_all) {
+    const DevScen& J = jobs[blockIdx.x];
+    const int H = J.H, W = J.W;
+    const int nparts = (H + 3) / 4;
+    const int* box = box_all + 4 * blockIdx.x;
+    const double* part = part_all + 2 * (int64_t)blockIdx.x * maxparts;
+    double* loss = loss_all + blockIdx.x;
     __shared__ double sh[2][256];
     double a = 0.0, b = 0.0;
     for (int i = threadIdx.x; i < nparts; i += 256) {
@@ -1279,11 +1291,14 @@ k_loss_final(int32_t H, int32_t W, int32_t kind, const int* __restrict__ box,
     }
 }
 
-__global__ void k_box_init(int* box, int32_t H, int32_t W) {
-    box[0] = H;
-    box[1] = -1;
-    box[2] = W;
-    box[3] = -1;
+__global__ void __launch_bounds__(256)
+k_box_init(const DevScen* __restrict__ jobs, int32_t n, int* __restrict__ box_all) {
+    for (int i = threadIdx.x; i < n; i += 256) {
+        box_all[4 * i] = jobs[i].H;
+        box_all[4 * i + 1] = -1;
+        box_all[4 * i + 2] = jobs[i].W;
+        box_all[4 * i + 3] = -1;
+    }
 }
 
 // ------------------------------------------------- checkpoints, parameters
@@ -1447,11 +1462,10 @@ hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d
     return hipGetLastError();
 }
 
-hipError_t launch_init_state(hipStream_t st, const DevScen& J, const uint8_t* ign,
-                             uint32_t* planes, float* yhat, int32_t* tign, int32_t* tout) {
-    uint32_t* other = planes == J.planes[0] ? J.planes[1] : J.planes[0];
-    hipLaunchKernelGGL(k_init_state, cell_grid(J.H, J.pitch * 32), dim3(256), 0, st, J.H, J.W,
-                       J.pitch, ign, planes, other, yhat, tign, tout);
+hipError_t launch_init_state(hipStream_t st, const DevScen* d_jobs, const int32_t* d_ib0,
+                             int32_t n, int32_t nblocks) {
+    if (nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_state, dim3(nblocks), dim3(256), 0, st, d_jobs, d_ib0, n);
     return hipGetLastError();
 }
 
@@ -1524,39 +1538,43 @@ hipError_t launch_grad_reduce(hipStream_t st, const double* gpart, const int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_loss(hipStream_t st, int32_t H, int32_t W, const float* yhat,
-                       const uint8_t* y, int32_t kind, float* lambda, int* d_box,
+hipError_t launch_loss(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
+                       int32_t max_h, const uint8_t* y, int32_t kind, float* lambda, int* d_box,
                        double* d_part, double* loss_out) {
-    const int nparts = (H + 3) / 4;
-    hipLaunchKernelGGL(k_box_init, dim3(1), dim3(1), 0, st, d_box, H, W);
-    hipLaunchKernelGGL(k_loss_box, cell_grid(H, W), dim3(256), 0, st, H, W, yhat, y, d_box);
-    hipLaunchKernelGGL(k_loss_terms, dim3(nparts), dim3(256), 0, st, H, W, yhat, y, kind, d_box,
-                       lambda, d_part);
-    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, st, H, W, kind, d_box, d_part,
-                       nparts, loss_out);
+    if (n <= 0) return hipSuccess;
+    const int maxparts = (max_h + 3) / 4;
+    hipLaunchKernelGGL(k_box_init, dim3(1), dim3(256), 0, st, d_jobs, n, d_box);
+    hipLaunchKernelGGL(k_loss_box, dim3(64, n), dim3(256), 0, st, d_jobs, d_cell0, y, d_box);
+    hipLaunchKernelGGL(k_loss_terms, dim3(maxparts, n), dim3(256), 0, st, d_jobs, d_cell0, y,
+                       kind, d_box, lambda, d_part, maxparts);
+    hipLaunchKernelGGL(k_loss_final, dim3(n), dim3(256), 0, st, d_jobs, kind, d_box, d_part,
+                       maxparts, loss_out);
     return hipGetLastError();
 }
 
 // ------------------------------------------------- step shape dispatch table
 
 namespace {
-#ifndef FS_STEP_THREADS
-#define FS_STEP_THREADS 256
-#endif
-constexpr int kStepThreads = FS_STEP_THREADS;
+// Work-group size per shape: 256 lanes for tiles of up to 16 rows, 512 for
+// 32-row tiles, whose taller regions hold more trials per step (measured on
+// the 4096 x 4096 workload: 512 lanes are 5-30 % faster there and 10 %
+// slower on 16-row tiles).
+constexpr int kThreadsShort = 256;
+constexpr int kThreadsTall = 512;
 using StepFn = void (*)(const DevScen*, const int32_t*, int32_t, int32_t, int32_t, int32_t,
                         int32_t, const float*, Rings, Sched, unsigned long long*);
 
 struct StepEntry {
-    int tr, tc, km;
+    int tr, tc, km, nt;
     bool adj;
     StepFn fn;
     int resident;   // work-groups resident at once on the device (0: not queried yet)
 };
 
-#define FS_SHAPE(TR, TC, KM)                                      \
-    {TR, TC, KM, false, &k_step<TR, TC, KM, false, kStepThreads>, 0}, \
-    {TR, TC, KM, true, &k_step<TR, TC, KM, true, kStepThreads>, 0},
+#define FS_SHAPE_NT(TR, TC, KM, NT)                           \
+    {TR, TC, KM, NT, false, &k_step<TR, TC, KM, false, NT>, 0}, \
+    {TR, TC, KM, NT, true, &k_step<TR, TC, KM, true, NT>, 0},
+#define FS_SHAPE(TR, TC, KM) FS_SHAPE_NT(TR, TC, KM, (TR >= 32 ? kThreadsTall : kThreadsShort))
 
 StepEntry kSteps[] = {
     FS_SHAPE(16, 4, 1) FS_SHAPE(16, 4, 4) FS_SHAPE(16, 4, 8) FS_SHAPE(16, 4, 16)
@@ -1569,9 +1587,11 @@ StepEntry kSteps[] = {
     FS_SHAPE(16, 2, 1) FS_SHAPE(16, 2, 4) FS_SHAPE(16, 2, 8) FS_SHAPE(16, 2, 16)
     FS_SHAPE(16, 1, 8) FS_SHAPE(16, 1, 16)
     FS_SHAPE(32, 2, 16) FS_SHAPE(32, 1, 16)
+    FS_SHAPE(32, 2, 32) FS_SHAPE(32, 1, 32) FS_SHAPE(32, 4, 32)
     FS_SHAPE(8, 2, 8) FS_SHAPE(8, 1, 8)
 };
 #undef FS_SHAPE
+#undef FS_SHAPE_NT
 
 const StepEntry* find_step(TileShape sh, bool adj) {
     for (const auto& e : kSteps)
@@ -1602,7 +1622,7 @@ hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_
         // capped by the caller and by the tile count
         if (e->resident == 0) {
             int per_cu = 0, dev = 0, cus = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->fn, kStepThreads, 0) !=
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->fn, e->nt, 0) !=
                     hipSuccess || per_cu < 1)
                 per_cu = 4;
             if (hipGetDevice(&dev) != hipSuccess ||
@@ -1613,7 +1633,7 @@ hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_
         }
         nb = std::max(1, std::min(std::min(grid, e->resident), ntiles));
     }
-    hipLaunchKernelGGL(e->fn, dim3(nb), dim3(kStepThreads), 0, st, d_jobs, d_tile_job, ntiles,
+    hipLaunchKernelGGL(e->fn, dim3(nb), dim3(e->nt), 0, st, d_jobs, d_tile_job, ntiles,
                        parity, t_off, ksteps, sched.in ? 0 : skip, lam, rings, sched, d_stats);
     return hipGetLastError();
 }

@@ -114,7 +114,7 @@ class Sim:
             pass
 
     # --------------------------------------------------------------- calls
-    def set_exec(self, tile_rows=16, tile_words=2, depth=16, skip=1):
+    def set_exec(self, tile_rows=32, tile_words=2, depth=32, skip=1):
         """skip: 0 process every tile, 1 (or True) device worklist, 2 per-tile test."""
         e = _abi.sim_exec(int(tile_rows), int(tile_words), int(depth), int(skip))
         self._check(self._lib.sim_set_exec(self._h, ctypes.byref(e)))

@@ -140,6 +140,8 @@ SHAPES = [
     dict(tile_rows=8, tile_words=8, depth=1, skip=False),
     dict(tile_rows=16, tile_words=2, depth=16, skip=2),
     dict(tile_rows=32, tile_words=1, depth=16, skip=1),
+    dict(tile_rows=32, tile_words=2, depth=32, skip=1),
+    dict(tile_rows=32, tile_words=4, depth=20, skip=2),
 ]
 
 
