@@ -42,8 +42,13 @@ HBM_PEAK_GBS = 8000.0
 # state, F = (1+p_veg)(1+p_den), elevation, wind speed and direction, and
 # writes 2 bits): 0.5 + 4 + 4 + 8.
 DENSE_BYTES_PER_CELL_STEP = 16.5
-DEFAULT_EXEC = dict(tile_rows=32, tile_words=2, depth=32, skip=True)
+DEFAULT_EXEC = dict(tile_rows=32, tile_words=2, depth=32, skip=1)
 PLAIN_EXEC = dict(tile_rows=16, tile_words=8, depth=1, skip=False)
+
+
+def km_bucket(depth):
+    """Halo depth of the step kernel that runs `depth` steps per launch."""
+    return next(k for k in (1, 4, 8, 16, 32) if k >= depth)
 
 
 def log(*a):
@@ -146,7 +151,9 @@ def leg_main(args, torch, Sim, synth):
     roof = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 3), "traffic": None,
-        "kernel": "k_step<{tile_rows},{tile_words},{depth},false>".format(**DEFAULT_EXEC),
+        "kernel": "k_step<{},{},{},false,{}>".format(
+            DEFAULT_EXEC["tile_rows"], DEFAULT_EXEC["tile_words"], km_bucket(DEFAULT_EXEC["depth"]),
+            DEFAULT_EXEC.get("threads") or (512 if DEFAULT_EXEC["tile_rows"] >= 32 else 256)),
         "launch_us": round(launch_s * 1e6, 2),
         "basis": "effective: dense-formulation bytes (16.5 B per cell-step) x cell-steps "
                  "per launch; the kernel reads fields only for cells with a trial",
@@ -337,9 +344,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--legs", default="main,plain,calib,batched,paper,cpu")
-    ap.add_argument("--exec", default=None, metavar="TR,TC,DEPTH,SKIP",
+    ap.add_argument("--exec", default=None, metavar="TR,TC,DEPTH,SKIP[,THREADS]",
                     help="execution shape of the main leg (tile rows, tile words, steps "
-                         "per launch, skip 0/1)")
+                         "per launch, skip 0/1/2, work-group size or 0 for the default)")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the main leg's shape on a mid-run state (the batched "
                          "leg always autotunes)")
@@ -371,8 +378,10 @@ def main():
         sys.exit(2)
     legs = set(args.legs.split(","))
     if args.exec:
-        tr, tc, dp, sk = (int(x) for x in args.exec.split(","))
-        DEFAULT_EXEC.update(tile_rows=tr, tile_words=tc, depth=dp, skip=bool(sk))
+        v = [int(x) for x in args.exec.split(",")]
+        DEFAULT_EXEC.update(tile_rows=v[0], tile_words=v[1], depth=v[2], skip=v[3])
+        if len(v) > 4:
+            DEFAULT_EXEC["threads"] = v[4]
 
     import torch
     import synth

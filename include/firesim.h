@@ -116,10 +116,12 @@ typedef struct {
  * tiles with no burning cell within reach are skipped: 0 = every tile is
  * processed, 1 = a device-built worklist (tiles that burn mark their
  * neighbours for the next launch; a grid of resident work-groups walks it),
- * 2 = every tile is launched and tests its neighbours' flags.  Every shape
+ * 2 = every tile is launched and tests its neighbours' flags.  threads is the
+ * work-group size (0 = the shape's default: 256 lanes for tiles of up to 16
+ * rows, 512 for 32-row tiles, which are also compiled with 256).  Every shape
  * produces bit-identical states. */
 typedef struct {
-    int32_t tile_rows, tile_words, depth, skip;
+    int32_t tile_rows, tile_words, depth, skip, threads;
 } sim_exec;
 
 /* Bytes of workspace sim_init needs for these scenarios.  ckpt_every and

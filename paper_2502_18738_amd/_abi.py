@@ -57,7 +57,8 @@ class sim_desc(ctypes.Structure):
 
 class sim_exec(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("tile_words", ctypes.c_int32),
-                ("depth", ctypes.c_int32), ("skip", ctypes.c_int32)]
+                ("depth", ctypes.c_int32), ("skip", ctypes.c_int32),
+                ("threads", ctypes.c_int32)]
 
 
 EXPORTS = (

@@ -269,7 +269,7 @@ fs::TileShape shape_of(const sim_exec& e) {
     int km = 1;
     for (int k : {1, 4, 8, 16, 32})
         if (k >= e.depth) { km = k; break; }
-    return fs::TileShape{e.tile_rows, e.tile_words, km};
+    return fs::TileShape{e.tile_rows, e.tile_words, km, e.threads};
 }
 
 int refresh_worklist(sim_handle* h, bool dup);
@@ -406,7 +406,7 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
     // default execution shape
     int32_t max_pitch = 0;
     for (const auto& s : h->L.s) max_pitch = std::max(max_pitch, s.pitch);
-    h->ex = sim_exec{32, 2, 32, 1};
+    h->ex = sim_exec{32, 2, 32, 1, 0};
     (void)max_pitch;
     h->sh = shape_of(h->ex);
 
@@ -518,8 +518,8 @@ int sim_set_exec(sim_handle* h, const sim_exec* e) {
     const fs::TileShape sh = shape_of(*e);
     if (!fs::step_shape_supported(sh, false) ||
         (h->calib() && !fs::step_shape_supported(sh, true)))
-        return h->fail(SIM_E_SHAPE, "tile %dx%d words with depth %d is not compiled in",
-                       e->tile_rows, e->tile_words, e->depth);
+        return h->fail(SIM_E_SHAPE, "tile %dx%d words with depth %d (%d threads) is not compiled in",
+                       e->tile_rows, e->tile_words, e->depth, e->threads);
     if (e->skip < 0 || e->skip > 2) return h->fail(SIM_E_ARG, "skip must be 0, 1 or 2");
     h->ex = *e;
     const bool same = sh.tr == h->sh.tr && sh.tc == h->sh.tc;
@@ -584,7 +584,7 @@ int ensure_qtable(sim_handle* h) {
 
 bool same_exec(const sim_exec& a, const sim_exec& b) {
     return a.tile_rows == b.tile_rows && a.tile_words == b.tile_words && a.depth == b.depth &&
-           a.skip == b.skip;
+           a.skip == b.skip && a.threads == b.threads;
 }
 
 // Replay (or capture, then replay) the launch sequence of T steps from the
@@ -703,7 +703,8 @@ int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best) {
     float best_ms = 1e30f;
     sim_exec best_ex = ex0;
     for (int c = 0; c < 2 * ns && !rc; ++c) {
-        const sim_exec ex{shapes[c % ns].tr, shapes[c % ns].tc, shapes[c % ns].km, 1 + c / ns};
+        const sim_exec ex{shapes[c % ns].tr, shapes[c % ns].tc, shapes[c % ns].km, 1 + c / ns,
+                          shapes[c % ns].nt};
         rc = sim_set_exec(h, &ex);
         if (!rc) rc = restore();
         if (!rc) rc = enqueue_run(h, h->st, T_probe, nullptr);   // warm-up

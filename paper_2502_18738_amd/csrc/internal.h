@@ -75,6 +75,7 @@ struct Sched {
 
 struct TileShape {
     int tr, tc, km;            // rows, words, halo depth (max steps per launch)
+    int nt;                    // work-group size; 0 = the shape's default (first entry)
 };
 
 // Kernel launchers (kernels.hip).  All enqueue on `st` and return the launch

@@ -1574,7 +1574,15 @@ struct StepEntry {
 #define FS_SHAPE_NT(TR, TC, KM, NT)                           \
     {TR, TC, KM, NT, false, &k_step<TR, TC, KM, false, NT>, 0}, \
     {TR, TC, KM, NT, true, &k_step<TR, TC, KM, true, NT>, 0},
-#define FS_SHAPE(TR, TC, KM) FS_SHAPE_NT(TR, TC, KM, (TR >= 32 ? kThreadsTall : kThreadsShort))
+// 32-row tiles come with both sizes (the default first): 512 lanes shorten
+// the per-step latency of a few busy tiles, 256 lanes give more resident
+// work-groups when many tiles are busy at once (large ensembles).
+#define FS_SHAPE(TR, TC, KM) FS_SHAPE_NT(TR, TC, KM, (TR >= 32 ? kThreadsTall : kThreadsShort)) \
+    FS_SHAPE_TALL256(TR, TC, KM)
+#define FS_SHAPE_TALL256(TR, TC, KM) FS_SHAPE_TALL256_##TR(TC, KM)
+#define FS_SHAPE_TALL256_8(TC, KM)
+#define FS_SHAPE_TALL256_16(TC, KM)
+#define FS_SHAPE_TALL256_32(TC, KM) FS_SHAPE_NT(32, TC, KM, kThreadsShort)
 
 StepEntry kSteps[] = {
     FS_SHAPE(16, 4, 1) FS_SHAPE(16, 4, 4) FS_SHAPE(16, 4, 8) FS_SHAPE(16, 4, 16)
@@ -1592,10 +1600,16 @@ StepEntry kSteps[] = {
 };
 #undef FS_SHAPE
 #undef FS_SHAPE_NT
+#undef FS_SHAPE_TALL256
+#undef FS_SHAPE_TALL256_8
+#undef FS_SHAPE_TALL256_16
+#undef FS_SHAPE_TALL256_32
 
 const StepEntry* find_step(TileShape sh, bool adj) {
     for (const auto& e : kSteps)
-        if (e.tr == sh.tr && e.tc == sh.tc && e.km == sh.km && e.adj == adj) return &e;
+        if (e.tr == sh.tr && e.tc == sh.tc && e.km == sh.km && e.adj == adj &&
+            (sh.nt == 0 || sh.nt == e.nt))
+            return &e;
     return nullptr;
 }
 }  // namespace
@@ -1605,7 +1619,7 @@ bool step_shape_supported(TileShape sh, bool adj) { return find_step(sh, adj) !=
 int step_shapes(TileShape* out, int max) {
     int n = 0;
     for (const auto& e : kSteps)
-        if (!e.adj && n < max) out[n++] = TileShape{e.tr, e.tc, e.km};
+        if (!e.adj && n < max) out[n++] = TileShape{e.tr, e.tc, e.km, e.nt};
     return n;
 }
 

@@ -114,16 +114,17 @@ class Sim:
             pass
 
     # --------------------------------------------------------------- calls
-    def set_exec(self, tile_rows=32, tile_words=2, depth=32, skip=1):
-        """skip: 0 process every tile, 1 (or True) device worklist, 2 per-tile test."""
-        e = _abi.sim_exec(int(tile_rows), int(tile_words), int(depth), int(skip))
+    def set_exec(self, tile_rows=32, tile_words=2, depth=32, skip=1, threads=0):
+        """skip: 0 process every tile, 1 (or True) device worklist, 2 per-tile test;
+        threads: work-group size (0 = the shape's default)."""
+        e = _abi.sim_exec(int(tile_rows), int(tile_words), int(depth), int(skip), int(threads))
         self._check(self._lib.sim_set_exec(self._h, ctypes.byref(e)))
 
     def get_exec(self):
         e = _abi.sim_exec()
         self._check(self._lib.sim_get_exec(self._h, ctypes.byref(e)))
         return dict(tile_rows=e.tile_rows, tile_words=e.tile_words, depth=e.depth,
-                    skip=int(e.skip))
+                    skip=int(e.skip), threads=int(e.threads))
 
     def autotune(self, T_probe: int = 32) -> dict:
         """Time every compiled execution shape over T_probe steps from the
@@ -131,7 +132,7 @@ class Sim:
         e = _abi.sim_exec()
         self._check(self._lib.sim_autotune(self._h, int(T_probe), ctypes.byref(e)))
         return dict(tile_rows=e.tile_rows, tile_words=e.tile_words, depth=e.depth,
-                    skip=int(e.skip))
+                    skip=int(e.skip), threads=int(e.threads))
 
     def use_graphs(self, on: bool = True):
         self._check(self._lib.sim_use_graphs(self._h, int(bool(on))))
