@@ -76,6 +76,9 @@ def _load():
     lib.fo_dpignite_cell.argtypes = [P, vp, i32, i32, vp]
     lib.fo_step.argtypes = [P, i32, vp, vp, vp, vp, dbl, vp]
     lib.fo_step.restype = i64
+    lib.fo_next_cell.argtypes = [P, i32, vp, i32, i32, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_int), dbl]
+    lib.fo_next_cell.restype = ctypes.c_uint8
     lib.fo_run.argtypes = [P, i32, i32, vp, vp, vp, dbl]
     lib.fo_run.restype = i64
     lib.fo_loss.argtypes = [i32, i32, vp, vp, i32, vp]
@@ -203,6 +206,26 @@ def dpignite_cell(scn, S, r, c, **kw):
     g = np.zeros(4, dtype=np.float64)
     lib.fo_dpignite_cell(pb.ref, S.ctypes.data, r, c, g.ctypes.data)
     return g
+
+
+def next_cells(scn, t, S_prev, rows, cols, tie_eps=1e-5, **kw):
+    """The per-cell rule of `step` at the listed cells only (for grids too
+    large to step whole): returns (next state, p_ignite, tie flag) arrays."""
+    lib = _load()
+    pb = _problem(scn, **kw)
+    S_prev = np.ascontiguousarray(S_prev, dtype=np.uint8)
+    n = len(rows)
+    nxt = np.zeros(n, np.uint8)
+    pv = np.zeros(n, np.float64)
+    tv = np.zeros(n, bool)
+    p = ctypes.c_double()
+    tie = ctypes.c_int()
+    for k in range(n):
+        nxt[k] = lib.fo_next_cell(pb.ref, int(t), S_prev.ctypes.data, int(rows[k]), int(cols[k]),
+                                  ctypes.byref(p), ctypes.byref(tie), float(tie_eps))
+        pv[k] = p.value
+        tv[k] = bool(tie.value)
+    return nxt, pv, tv
 
 
 def step(scn, t, S_prev, tie_eps=1e-5, yhat=None, **kw):

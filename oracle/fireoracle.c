@@ -236,6 +236,34 @@ static int has_burning_neighbour(const fo_problem* pb, const uint8_t* S, int32_t
     return 0;
 }
 
+uint8_t fo_next_cell(const fo_problem* pb, int32_t t, const uint8_t* S_prev, int32_t r,
+                     int32_t c, double* p_out, int* tie_out, double tie_eps)
+{
+    const int64_t j = (int64_t)r * pb->W + c;
+    const uint8_t s = S_prev[j];
+    uint8_t next;
+    double p = 0.0;
+    int tie = 0;
+    if (s == 2) {                     /* burned is absorbing */
+        next = 2;
+    } else if (s == 1) {              /* keep burning w.p. p_continue */
+        double u_cont;
+        fo_draws(pb, t, j, NULL, &u_cont);
+        next = (u_cont < pb->p_continue) ? 1 : 2;
+    } else if (!has_burning_neighbour(pb, S_prev, r, c)) {
+        next = 0;                     /* no trial without a burning neighbour */
+    } else {
+        double u_ign;
+        p = fo_pignite_cell(pb, S_prev, r, c);
+        fo_draws(pb, t, j, &u_ign, NULL);
+        next = (u_ign < (double)(float)p) ? 1 : 0;
+        tie = fabs(u_ign - p) <= tie_eps;
+    }
+    if (p_out) *p_out = p;
+    if (tie_out) *tie_out = tie;
+    return next;
+}
+
 int64_t fo_step(const fo_problem* pb, int32_t t, const uint8_t* S_prev, uint8_t* S_next,
                 double* yhat, uint8_t* tie, double tie_eps, double* pmap)
 {
@@ -243,29 +271,12 @@ int64_t fo_step(const fo_problem* pb, int32_t t, const uint8_t* S_prev, uint8_t*
     for (int32_t r = 0; r < pb->H; ++r)
         for (int32_t c = 0; c < pb->W; ++c) {
             const int64_t j = (int64_t)r * pb->W + c;
-            const uint8_t s = S_prev[j];
-            double p = 0.0;
-            if (tie) tie[j] = 0;
-            if (s == 2) {                     /* burned is absorbing */
-                S_next[j] = 2;
-            } else if (s == 1) {              /* keep burning w.p. p_continue */
-                double u_cont;
-                fo_draws(pb, t, j, NULL, &u_cont);
-                S_next[j] = (u_cont < pb->p_continue) ? 1 : 2;
-            } else if (!has_burning_neighbour(pb, S_prev, r, c)) {
-                S_next[j] = 0;                /* no trial without a burning neighbour */
-            } else {
-                double u_ign;
-                p = fo_pignite_cell(pb, S_prev, r, c);
-                fo_draws(pb, t, j, &u_ign, NULL);
-                int ignite = u_ign < (double)(float)p;
-                S_next[j] = ignite ? 1 : 0;
-                if (ignite && yhat) yhat[j] = p;
-                if (fabs(u_ign - p) <= tie_eps) {
-                    ++ties;
-                    if (tie) tie[j] = 1;
-                }
-            }
+            double p;
+            int tj;
+            S_next[j] = fo_next_cell(pb, t, S_prev, r, c, &p, &tj, tie_eps);
+            if (S_prev[j] == 0 && S_next[j] == 1 && yhat) yhat[j] = p;
+            ties += tj;
+            if (tie) tie[j] = (uint8_t)tj;
             if (pmap) pmap[j] = p;
         }
     return ties;

@@ -85,6 +85,12 @@ void fo_pignite_map(const fo_problem* pb, const uint8_t* S, double* out);
 void fo_dpignite_cell(const fo_problem* pb, const uint8_t* S, int32_t r, int32_t c,
                       double g[4]);
 
+/* The state at step t of cell (r, c) from S(t-1) = S_prev (the per-cell rule
+ * of fo_step).  p_out (nullable) receives p_ignite for ignition trials, else 0;
+ * tie_out (nullable) 1 for an ignition trial with |u - p| <= tie_eps. */
+uint8_t fo_next_cell(const fo_problem* pb, int32_t t, const uint8_t* S_prev, int32_t r,
+                     int32_t c, double* p_out, int* tie_out, double tie_eps);
+
 /* One synchronous step producing S(t) from S(t-1) = S_prev.
  *   yhat  (nullable): p_ignite written for cells that ignite at this step
  *   tie   (nullable): set to 1 for ignition trials with |u - p| <= tie_eps

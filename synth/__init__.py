@@ -12,6 +12,7 @@ from .fields import (  # noqa: F401
     PARAMS_TRUE,
     C_NORMALISER,
     make_plain,
+    make_rough,
     make_lakes,
     config0,
     config1,

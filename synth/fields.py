@@ -132,6 +132,26 @@ def _ignite(veg, cells):
     return ign
 
 
+def make_rough(H, W, seed, *, nonburn_frac=0.05, e_max=5.0, T=100):
+    """Unsmoothed fields for very large grids (index and edge tests at the
+    paper's largest side): iid classes and non-burnable cells, iid elevation in
+    [0, e_max] m, iid per-cell wind (0-12 m/s, [0, 360) degrees).  Generated
+    in float32 draws so that a 14 000 x 14 000 grid takes seconds."""
+    rng = np.random.default_rng(seed)
+    veg = VEG_CLASSES[rng.integers(0, 4, size=(H, W), dtype=np.int8)]
+    den = DEN_CLASSES[rng.integers(0, 3, size=(H, W), dtype=np.int8)]
+    veg = np.where(rng.random((H, W), dtype=np.float32) < nonburn_frac, np.float32(-1.0), veg)
+    elev = rng.random((H, W), dtype=np.float32) * np.float32(e_max)
+    ws = rng.random((H, W), dtype=np.float32) * np.float32(12.0)
+    wd = rng.random((H, W), dtype=np.float32) * np.float32(360.0)
+    ign = np.zeros((H, W), dtype=np.uint8)
+    s = Scenario(H=H, W=W, p_veg=_f32(veg), p_den=_f32(den), elevation=_f32(elev),
+                 wind_speed=_f32(ws), wind_dir=_f32(wd),
+                 wind_speed_scalar=0.0, wind_dir_scalar=0.0,
+                 init_burning=ign, seed=seed, scenario_id=0, T=T)
+    return s.with_params(*s.params)
+
+
 def make_plain(H, W, seed, *, nonburn_frac=0.05, e_sigma=8.0, e_max=300.0,
                wind_speed=5.0, wind_dir=45.0, ignitions=None, T=100,
                scenario_id=0, params=None):

@@ -591,3 +591,56 @@ def test_ensemble_arrival_matches_oracle(Sim):
     assert np.array_equal(c, ref)
     with pytest.raises(Exception):
         sim.arrival(3, 3)
+
+
+# ------------------------------------------------- the paper's largest side
+
+def test_largest_side_sampled_parity(Sim):
+    """14 000 x 14 000 (the paper's largest side) with rough per-cell fields:
+    fires at the four corners, the middle of each edge and the centre; p_ignite
+    and one step at every cell within 12 of them and at random cells, against
+    the oracle's per-cell rule (the grid is too large to step whole on the CPU)."""
+    import torch
+    import bench
+    N = 14000
+    s = synth.make_rough(N, N, 91)
+    S0 = np.zeros((N, N), np.uint8)
+    centres = [(2, 2), (2, N - 3), (N - 3, 2), (N - 3, N - 3), (0, N // 2), (N - 1, N // 2),
+               (N // 2, 0), (N // 2, N - 1), (N // 2, N // 2)]
+    for cy, cx in centres:
+        r0, r1, c0, c1 = max(0, cy - 6), min(N, cy + 7), max(0, cx - 6), min(N, cx + 7)
+        yy, xx = np.mgrid[r0:r1, c0:c1]
+        d = np.hypot(yy - cy, xx - cx)
+        win = S0[r0:r1, c0:c1]
+        win[d < 3] = 2
+        win[(d >= 3) & (d < 5)] = 1
+        win[s.p_veg[r0:r1, c0:c1] <= -1] = 0
+    rows, cols = [], []
+    for cy, cx in centres:
+        for r in range(max(0, cy - 12), min(N, cy + 13)):
+            for c in range(max(0, cx - 12), min(N, cx + 13)):
+                rows.append(r)
+                cols.append(c)
+    rng = np.random.default_rng(7)
+    rows = np.array(rows + rng.integers(0, N, 3000).tolist())
+    cols = np.array(cols + rng.integers(0, N, 3000).tolist())
+    t0 = 700
+    say("largest side: oracle at", len(rows), "cells")
+    nxt, p_ref, ties = oracle.next_cells(oracle.Problem(s), t0 + 1, S0, rows, cols)
+    assert (p_ref > 0).sum() > 100
+    sim = Sim([s], exec=bench.DEFAULT_EXEC)
+    sim.set_state(0, synth.encode_planes(S0), t0)
+    ri = torch.as_tensor(rows, device="cuda")
+    ci = torch.as_tensor(cols, device="cuda")
+    p = sim.pignite(0)[ri, ci].cpu().numpy().astype(np.float64)
+    nz = p_ref > 0
+    assert np.all(p[~nz] == 0.0)
+    assert np.max(np.abs(p[nz] - p_ref[nz]) / p_ref[nz]) <= 1e-5
+    sim.run(1)
+    st = sim.get_state(0)[:, ri, ci].cpu().numpy()
+    g = st[0].astype(np.uint8) + 2 * st[1].astype(np.uint8)
+    assert not np.any((g != nxt) & ~ties), np.argwhere((g != nxt) & ~ties)[:5]
+    say("largest side: ignitions", int(((S0[rows, cols] == 0) & (g == 1)).sum()),
+        "near ties", int(ties.sum()))
+    del sim
+    torch.cuda.synchronize()

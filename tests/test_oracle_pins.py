@@ -477,3 +477,15 @@ def test_jaccard_and_manhattan_closed_forms(oracle_lib):
     assert oracle_lib.jaccard(A, B) == pytest.approx(1 / 7)
     assert oracle_lib.manhattan([1, 5, 9], [2, 5, 7]) == 3.0
     assert oracle_lib.manhattan([3, 3], [3, 3]) == 0.0
+
+
+def test_next_cells_is_the_rule_of_step(oracle_lib):
+    """The per-cell rule used for sampled checks on very large grids is the
+    rule of the whole-grid step."""
+    s, S = random_small(23, 31, 41, per_cell_wind=True)
+    full, tie, pmap, _ = oracle_lib.step(s, 9, S, tie_eps=1e-3)
+    rr, cc = np.divmod(np.arange(s.H * s.W), s.W)
+    nxt, p, t = oracle_lib.next_cells(s, 9, S, rr, cc, tie_eps=1e-3)
+    assert np.array_equal(nxt.reshape(S.shape), full)
+    assert np.array_equal(t.reshape(S.shape), tie.astype(bool))
+    np.testing.assert_array_equal(p.reshape(S.shape), pmap)
