@@ -63,6 +63,22 @@ extern "C" {
 /* sim_init flags */
 #define SIM_F_CALIB 1u        /* keep the accumulator and state checkpoints   */
 #define SIM_F_STATS 2u        /* count processed tiles, trials and near ties  */
+#define SIM_F_TIELOG 4u       /* log ignition trials with |draw - p| <= 2e-5   */
+
+/* Near-tie log (SIM_F_TIELOG): one record per ignition trial whose uniform
+ * draw lies within 2e-5 of its FP32 p_ignite (Eq. 9), at most SIM_TIELOG_CAP
+ * records since the last reset.  Such trials are the ones whose decision may
+ * differ from an FP64 evaluation of the same step. */
+#define SIM_TIELOG_CAP (1 << 20)
+typedef struct {
+    int32_t scenario;   /* index of the scenario in the handle */
+    int32_t step;       /* step t of the trial (S(t) is being produced) */
+    int64_t cell;       /* r * W + c */
+    float p_ignite;     /* FP32 p_ignite of the trial */
+    float draw;         /* the uniform draw u of the trial */
+    int32_t ignited;    /* u < p_ignite */
+    int32_t reserved;
+} sim_tie;
 
 /* loss kinds of sim_loss_grad (Eq. 10) */
 #define SIM_LOSS_BCE 0        /* BCE-with-logits over the bounding-box crop   */
@@ -256,6 +272,14 @@ SIM_API int sim_overlap(sim_handle* h, int32_t s, const uint8_t* target, int64_t
  * one grid shape (SIM_E_SHAPE otherwise); typically they differ only in seed.
  * counts / (number of runs accumulated) is the arrival-probability map. */
 SIM_API int sim_arrival(sim_handle* h, int32_t s0, int32_t n, uint32_t* counts);
+
+/* Copy the near-tie log (handle created with SIM_F_TIELOG) to `out` (device
+ * array of `capacity` records, nullable when capacity is 0): the first
+ * min(logged, capacity, SIM_TIELOG_CAP) records, in no particular order.
+ * *count (host) receives the number of trials logged since the last reset,
+ * which exceeds SIM_TIELOG_CAP when records were dropped.  Waits for the
+ * stream.  (SIM_E_STATE without SIM_F_TIELOG.) */
+SIM_API int sim_tielog(sim_handle* h, sim_tie* out, int64_t capacity, int64_t* count);
 
 /* Counters accumulated since the last reset with SIM_F_STATS (host array of
  * 4): processed tiles, ignition + continue trials, ignition trials with

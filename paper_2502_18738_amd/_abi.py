@@ -22,6 +22,8 @@ SIM_E_STATE = -6
 
 SIM_F_CALIB = 1
 SIM_F_STATS = 2
+SIM_F_TIELOG = 4
+SIM_TIELOG_CAP = 1 << 20
 
 SIM_LOSS_BCE = 0
 SIM_LOSS_BCE_MSE = 1
@@ -55,6 +57,12 @@ class sim_desc(ctypes.Structure):
                 ("params", sim_params), ("f", sim_fields)]
 
 
+class sim_tie(ctypes.Structure):
+    _fields_ = [("scenario", ctypes.c_int32), ("step", ctypes.c_int32), ("cell", ctypes.c_int64),
+                ("p_ignite", ctypes.c_float), ("draw", ctypes.c_float),
+                ("ignited", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 class sim_exec(ctypes.Structure):
     _fields_ = [("tile_rows", ctypes.c_int32), ("tile_words", ctypes.c_int32),
                 ("depth", ctypes.c_int32), ("skip", ctypes.c_int32),
@@ -66,7 +74,7 @@ EXPORTS = (
     "sim_get_step", "sim_set_params", "sim_reset", "sim_get_state", "sim_set_state",
     "sim_pignite", "sim_accumulator", "sim_adjoint", "sim_loss_grad", "sim_stats",
     "sim_last_error", "sim_destroy", "sim_version", "sim_autotune", "sim_use_graphs",
-    "sim_set_adjoint", "sim_set_wind", "sim_ignite", "sim_counts", "sim_overlap", "sim_arrival",
+    "sim_set_adjoint", "sim_set_wind", "sim_ignite", "sim_counts", "sim_overlap", "sim_arrival", "sim_tielog",
 )
 
 _lib = None
@@ -116,6 +124,7 @@ def load():
         "sim_counts": (ctypes.c_int, [H, vp]),
         "sim_overlap": (ctypes.c_int, [H, i32, vp, vp]),
         "sim_arrival": (ctypes.c_int, [H, i32, i32, vp]),
+        "sim_tielog": (ctypes.c_int, [H, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

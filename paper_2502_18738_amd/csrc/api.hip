@@ -37,7 +37,7 @@ struct ScenLayout {
 
 struct Layout {
     size_t err, stats, box, part, jobs, tile_job, adj_jobs, adj_tile_job, gpart, ranges, lam,
-        cell0, bl0, ib0, gpart_tmap, masks, adj_masks, total;
+        cell0, bl0, ib0, gpart_tmap, masks, adj_masks, tielog, tie_n, total;
     int32_t mask_words, adj_mask_words;
     int64_t total_cells;
     int32_t tmap_blocks;
@@ -61,6 +61,11 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
     int64_t max_h = 0;
     L->err = take(64);
     L->stats = take(4 * sizeof(unsigned long long));
+    L->tielog = L->tie_n = 0;
+    if (flags & SIM_F_TIELOG) {
+        L->tielog = take(sizeof(sim_tie) * (size_t)SIM_TIELOG_CAP);
+        L->tie_n = take(sizeof(unsigned long long));
+    }
     L->box = take(4 * sizeof(int) * (size_t)n);
     for (int i = 0; i < n; ++i) max_h = std::max<int64_t>(max_h, d[i].H);
     L->max_h = (int32_t)max_h;
@@ -335,6 +340,9 @@ int reset_state(sim_handle* h) {
     if (rc) return rc;
     rc = h->hip(hipMemsetAsync(h->d_stats(), 0, 4 * sizeof(unsigned long long), h->st),
                 "clear stats");
+    if (!rc && (h->flags & SIM_F_TIELOG))
+        rc = h->hip(hipMemsetAsync(h->ws + h->L.tie_n, 0, sizeof(unsigned long long), h->st),
+                    "clear tie log");
     if (rc) return rc;
     h->launches = 0;
     if (h->calib()) return save_ckpt(h, 0);
@@ -365,7 +373,7 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
     std::string why;
     int rc = check_descs(descs, n, &why);
     if (rc) { g_init_error = why; return rc; }
-    if (flags & ~(uint32_t)(SIM_F_CALIB | SIM_F_STATS)) {
+    if (flags & ~(uint32_t)(SIM_F_CALIB | SIM_F_STATS | SIM_F_TIELOG)) {
         g_init_error = "unknown flag bits";
         return SIM_E_ARG;
     }
@@ -419,6 +427,11 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
         J.H = d.H;
         J.W = d.W;
         J.pitch = s.pitch;
+        J.sidx = i;
+        if (flags & SIM_F_TIELOG) {
+            J.tielog = h->ws + h->L.tielog;
+            J.tie_n = reinterpret_cast<unsigned long long*>(h->ws + h->L.tie_n);
+        }
         J.t_base = 0;
         J.t_end = INT_MAX;
         J.scen_id = d.scenario_id;
@@ -1068,6 +1081,27 @@ int sim_arrival(sim_handle* h, int32_t s0, int32_t n, uint32_t* counts) {
             return h->fail(SIM_E_SHAPE, "scenario %d has a different grid shape than %d", s, s0);
     return h->hip(fs::launch_arrival(h->st, h->d_jobs(), h->job[s0], s0, n, h->parity, counts),
                   "arrival counts");
+}
+
+int sim_tielog(sim_handle* h, sim_tie* out, int64_t capacity, int64_t* count) {
+    static_assert(sizeof(sim_tie) == sizeof(fs::TieRec), "tie record layout");
+    static_assert(SIM_TIELOG_CAP == fs::kTieLogCap, "tie log capacity");
+    if (!h) return SIM_E_ARG;
+    if (!(h->flags & SIM_F_TIELOG)) return h->fail(SIM_E_STATE, "the handle has no tie log (SIM_F_TIELOG)");
+    if (!count || capacity < 0 || (capacity > 0 && !out))
+        return h->fail(SIM_E_ARG, "count must be non-NULL and out non-NULL when capacity > 0");
+    unsigned long long n = 0;
+    int rc = h->hip(hipMemcpyAsync(&n, h->ws + h->L.tie_n, sizeof n, hipMemcpyDeviceToHost, h->st),
+                    "read tie count");
+    if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (rc) return rc;
+    const int64_t m = std::min<int64_t>(std::min<int64_t>((int64_t)n, capacity), SIM_TIELOG_CAP);
+    if (m > 0)
+        rc = h->hip(hipMemcpyAsync(out, h->ws + h->L.tielog, sizeof(sim_tie) * (size_t)m,
+                                   hipMemcpyDeviceToDevice, h->st), "copy tie log");
+    if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (!rc) *count = (int64_t)n;
+    return rc;
 }
 
 int sim_stats(sim_handle* h, uint64_t out[4]) {

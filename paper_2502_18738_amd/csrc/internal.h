@@ -37,7 +37,7 @@ struct DevScen {
     uint32_t seed_lo, seed_hi;
     float inv_l, inv_l_diag;   // 1 / l and 1 / (sqrt(2) l) of Eq. 1
     float p_h, a, c1, c2, p_continue, c;
-    int32_t pad0;
+    int32_t sidx;              // index of the scenario in its handle
     const float* elev;         // caller's elevation field
     const float4* rec;         // per-cell record
     const float* th8;          // slope (Eq. 1, degrees) toward each of the 8 neighbours
@@ -53,6 +53,18 @@ struct DevScen {
     uint32_t* ckpt;            // checkpoint store (forward) / own segment (adjoint)
     double* gpart;             // per-tile gradient partials (adjoint jobs)
     int64_t lam_off;           // offset of this scenario's dL/dyhat grid
+    void* tielog;              // near-tie records (sim_tie layout) or nullptr
+    unsigned long long* tie_n; // number of trials logged
+};
+
+// Near-tie log: capacity and window of the records (|u - p| <= kTieLogEps).
+constexpr long long kTieLogCap = 1 << 20;
+constexpr float kTieLogEps = 2e-5f;
+struct TieRec {
+    int32_t scenario, step;
+    int64_t cell;
+    float p, u;
+    int32_t ignited, reserved;
 };
 
 // Step-ring attach set of the adjoint (Sec. 2.3): ignition steps t with

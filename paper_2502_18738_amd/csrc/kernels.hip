@@ -605,6 +605,19 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     if (interior) {
                         ++n_trials;
                         if (fabsf(u - P) <= kTieEps) ++n_ties;
+                        if (!ADJ && J.tielog && fabsf(u - P) <= kTieLogEps) {
+                            const unsigned long long n = atomicAdd(J.tie_n, 1ull);
+                            if (n < (unsigned long long)kTieLogCap) {
+                                FS_GLOBAL TieRec* tr = gmem(reinterpret_cast<TieRec*>(J.tielog)) + n;
+                                tr->scenario = J.sidx;
+                                tr->step = t;
+                                tr->cell = j;
+                                tr->p = P;
+                                tr->u = u;
+                                tr->ignited = u < P ? 1 : 0;
+                                tr->reserved = 0;
+                            }
+                        }
                     }
                 }
             }

@@ -41,6 +41,7 @@ class Sim:
 
     def __init__(self, scenarios: Sequence, *, device="cuda", calib: bool = False,
                  stats: bool = False, ckpt_every: int = 20, T_max: Optional[int] = None,
+                 tielog: bool = False,
                  exec: Optional[dict] = None, stream: Optional[torch.cuda.Stream] = None):
         self._lib = _abi.load()
         self.device = torch.device(device)
@@ -49,7 +50,8 @@ class Sim:
         self.offsets = np.concatenate([[0], np.cumsum([h * w for h, w in self.shapes])])
         self.calib = bool(calib)
         self.p_continue = [float(np.float32(s.p_continue)) for s in scenarios]
-        flags = (_abi.SIM_F_CALIB if calib else 0) | (_abi.SIM_F_STATS if stats else 0)
+        flags = ((_abi.SIM_F_CALIB if calib else 0) | (_abi.SIM_F_STATS if stats else 0)
+                 | (_abi.SIM_F_TIELOG if tielog else 0))
         if calib and T_max is None:
             T_max = max(int(getattr(s, "T", 0)) for s in scenarios)
         T_max = int(T_max or 0)
@@ -272,6 +274,24 @@ class Sim:
             raise ValueError("counts must be a contiguous int32 tensor of H*W cells")
         self._check(self._lib.sim_arrival(self._h, int(s0), n, _ptr(counts)))
         return counts
+
+    def tie_log(self):
+        """Near-tie records logged since the last reset (handle created with
+        tielog=True): a numpy structured array with fields scenario, step,
+        cell, p_ignite, draw, ignited, sorted by (scenario, step, cell); and the
+        number of trials logged (more than the records if the log overflowed)."""
+        n = ctypes.c_int64()
+        self._check(self._lib.sim_tielog(self._h, None, 0, ctypes.byref(n)))
+        m = min(int(n.value), _abi.SIM_TIELOG_CAP)
+        buf = torch.empty(max(m, 1) * ctypes.sizeof(_abi.sim_tie), dtype=torch.uint8,
+                          device=self.device)
+        self._check(self._lib.sim_tielog(self._h, _ptr(buf), m, ctypes.byref(n)))
+        dt = np.dtype([("scenario", "<i4"), ("step", "<i4"), ("cell", "<i8"),
+                       ("p_ignite", "<f4"), ("draw", "<f4"), ("ignited", "<i4"),
+                       ("reserved", "<i4")])
+        rec = buf[: m * dt.itemsize].cpu().numpy().view(dt)
+        rec = np.sort(rec, order=["scenario", "step", "cell"])
+        return rec, int(n.value)
 
     def stats(self) -> dict:
         v = (ctypes.c_uint64 * 4)()

@@ -43,6 +43,7 @@ def test_struct_layout_matches_header():
     assert ctypes.sizeof(_abi.sim_fields) == 64
     assert ctypes.sizeof(_abi.sim_desc) == 24 + 20 + 4 + 64
     assert ctypes.sizeof(_abi.sim_exec) == 20
+    assert ctypes.sizeof(_abi.sim_tie) == 32
 
 
 def fake_desc(H=64, W=80, **kw):

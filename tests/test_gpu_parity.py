@@ -644,3 +644,46 @@ def test_largest_side_sampled_parity(Sim):
         "near ties", int(ties.sum()))
     del sim
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------- near-tie log
+
+def test_tie_log_covers_the_oracle_ties(Sim):
+    """Every ignition trial the oracle counts as a near tie (|u - p| <= 1e-5 in
+    FP64) is in the GPU's near-tie log (|u - p32| <= 2e-5) at the same step and
+    cell; the log's records are consistent; and where the trajectories first
+    differ, each differing cell is a logged trial decided as the GPU state says."""
+    s = synth.make_lakes(384, 384, 8, T=160, n_ignitions=8)
+    T = 160
+    states, ties = oracle_traj(s, T)
+    sim = Sim([s], tielog=True)
+    first = None
+    for t in range(1, T + 1):
+        sim.run(1)
+        g = gstate(sim)
+        if not np.array_equal(g, states[t]):
+            first = (t, g)
+            break
+    log, n = sim.tie_log()
+    assert n == len(log) and n > 0
+    assert np.all(np.abs(log["draw"].astype(np.float64) - log["p_ignite"]) <= 2e-5)
+    assert np.array_equal(log["ignited"] == 1, log["draw"] < log["p_ignite"])
+    assert np.all(log["scenario"] == 0)
+    last = first[0] if first else T
+    # the oracle also flags draws near p = 0 at fuel-less cells, whose decision
+    # no rounding can change (the kernel never draws for them)
+    fuel = ((1.0 + s.p_veg.astype(np.float64)) * (1.0 + s.p_den.astype(np.float64)) > 0).ravel()
+    for t in range(1, last + 1):
+        want = set(np.flatnonzero(ties[t].ravel() & fuel).tolist())
+        got = set(log["cell"][log["step"] == t].tolist())
+        assert want <= got, (t, sorted(want - got)[:5])
+    if first:
+        t, g = first
+        bad = np.flatnonzero(g.ravel() != states[t].ravel())
+        at = log[log["step"] == t]
+        idx = {int(c): k for k, c in enumerate(at["cell"])}
+        for c in bad:
+            assert int(c) in idx
+            assert at["ignited"][idx[int(c)]] == (g.ravel()[c] == 1)
+    say("tie log:", n, "records; oracle ties:", int(sum(x.sum() for x in ties[1:last + 1])),
+        "first difference at", first[0] if first else None)
