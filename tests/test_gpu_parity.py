@@ -687,3 +687,81 @@ def test_tie_log_covers_the_oracle_ties(Sim):
             assert at["ignited"][idx[int(c)]] == (g.ravel()[c] == 1)
     say("tie log:", n, "records; oracle ties:", int(sum(x.sum() for x in ties[1:last + 1])),
         "first difference at", first[0] if first else None)
+
+
+# ------------------------------------ the other workloads at their full sizes
+
+def oracle_run_with_cone(s, T, want_yhat=False):
+    """The oracle's run from the ignition with the near-tie light cone grown
+    on the fly (one cell per step): cells outside `allowed` cannot differ
+    between two correct implementations.  Returns (S_T, allowed, yhat)."""
+    pb = oracle.Problem(s)
+    S = oracle.initial_state(s)
+    allowed = np.zeros(S.shape, bool)
+    yhat = (S == 1).astype(np.float64) if want_yhat else None
+    for t in range(1, T + 1):
+        S, tie, _, _ = oracle.step(pb, t, S, tie_eps=TIE, yhat=yhat)
+        if allowed.any():
+            allowed = maximum_filter(allowed.astype(np.uint8), size=3) > 0
+        allowed |= tie
+    return S, allowed, yhat
+
+
+def test_config1_full_run_parity(Sim):
+    """1024 x 1024 lakes, per-cell wind, 5 ignitions, 500 steps, with the
+    benchmark's default shape: the final state equals the oracle's outside the
+    light cones of near ties."""
+    import bench
+    s = synth.config1()
+    say("config1: oracle 500 steps")
+    S_ref, allowed, _ = oracle_run_with_cone(s, s.T)
+    sim = Sim([s], exec=bench.DEFAULT_EXEC)
+    sim.run(s.T)
+    g = gstate(sim)
+    bad = (g != S_ref) & ~allowed
+    assert not bad.any(), np.argwhere(bad)[:5]
+    say("config1: burned", int((g != 0).sum()), "cells; cone", int(allowed.sum()),
+        "; differing", int((g != S_ref).sum()))
+
+
+def test_config3_subset_batched_parity(Sim):
+    """Four of the 256 ensemble scenarios at their full sizes, batched in one
+    handle with the autotuned shape and graph replay, 300 steps each: every
+    scenario equals the oracle outside near-tie light cones."""
+    sizes = synth.config3_sizes()
+    pick = sorted(range(64), key=lambda b: sizes[b][0] * sizes[b][1])[:4]
+    scs = [synth.config3_scenario(b) for b in pick]
+    sim = Sim(scs)
+    sim.run(150)
+    ex = sim.autotune(64)
+    sim.reset()
+    sim.run(300)
+    say("config3 subset", [(s.H, s.W) for s in scs], "shape", ex)
+    for b, s in enumerate(scs):
+        S_ref, allowed, _ = oracle_run_with_cone(s, 300)
+        g = gstate(sim, b)
+        assert not np.any((g != S_ref) & ~allowed), b
+
+
+def test_config4_subset_accumulator_parity(Sim):
+    """Two of the 64 calibration scenarios at full size (1024 x 1024, 200
+    steps, checkpoints every 20) with the shape the calibration benchmark
+    tunes: the accumulator y-hat equals the oracle's (1e-5 relative) and the
+    state is equal, outside near-tie light cones."""
+    cases = [synth.config4_scenario(b) for b in (0, 1)]
+    scs = [c[0].with_params(*c[1]) for c in cases]
+    tune = Sim(scs)
+    tune.run(100)
+    ex = tune.autotune(20)
+    del tune
+    sim = Sim(scs, calib=True, T_max=200, ckpt_every=20, exec=ex)
+    sim.run(200)
+    for b, s in enumerate(scs):
+        S_ref, allowed, y_ref = oracle_run_with_cone(s, 200, want_yhat=True)
+        g = gstate(sim, b)
+        y = sim.accumulator(b).cpu().numpy().astype(np.float64)
+        ok = ~allowed
+        assert not np.any((g != S_ref) & ok), b
+        nz = ok & (y_ref > 0)
+        assert np.all(y[ok & (y_ref == 0)] == 0.0)
+        assert np.max(np.abs(y[nz] - y_ref[nz]) / y_ref[nz]) <= 1e-5
