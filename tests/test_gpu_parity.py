@@ -765,3 +765,43 @@ def test_config4_subset_accumulator_parity(Sim):
         nz = ok & (y_ref > 0)
         assert np.all(y[ok & (y_ref == 0)] == 0.0)
         assert np.max(np.abs(y[nz] - y_ref[nz]) / y_ref[nz]) <= 1e-5
+
+
+# ------------------------------------------------------------ degenerate cases
+
+def degenerate_cases():
+    out = []
+    one = synth.make_plain(1, 1, 21, ignitions=[(0, 0)], T=10)
+    out.append(("1x1 burning", one))
+    quiet = synth.make_lakes(70, 90, 22, T=40)
+    quiet.init_burning = np.zeros_like(quiet.init_burning)
+    out.append(("no fire", quiet))
+    out.append(("p_h = 0", synth.make_lakes(80, 64, 23, T=40).with_params(p_h=0.0)))
+    out.append(("p_continue = 1", synth.make_lakes(80, 64, 24, T=40).with_params(p_continue=1.0)))
+    out.append(("p_continue = 0", synth.make_lakes(80, 64, 25, T=40).with_params(p_continue=0.0)))
+    wall = synth.make_plain(60, 70, 26, ignitions=[(30, 35)], T=30)
+    wall.p_veg = np.where(wall.init_burning != 0, wall.p_veg, np.float32(-1.0)).astype(np.float32)
+    out.append(("no fuel around the ignition", wall))
+    out.append(("one row", synth.make_plain(1, 333, 27, ignitions=[(0, 100), (0, 300)], T=60)))
+    out.append(("one column", synth.make_plain(290, 1, 28, ignitions=[(5, 0), (200, 0)], T=60)))
+    return out
+
+
+@pytest.mark.parametrize("name,s", degenerate_cases(), ids=lambda v: v if isinstance(v, str) else "")
+def test_degenerate_cases_match_oracle(Sim, name, s):
+    T = s.T
+    states, ties = oracle_traj(s, T)
+    for ex in (None, dict(tile_rows=8, tile_words=1, depth=8, skip=1),
+               dict(tile_rows=32, tile_words=2, depth=32, skip=2)):
+        sim = Sim([s], exec=ex)
+        sim.run(T)
+        check_light_cone(gstate(sim), states, ties, T)
+    S_T = states[T]
+    if name == "no fire":
+        assert not S_T.any()
+    if name == "p_h = 0" or name == "no fuel around the ignition":
+        assert np.array_equal(S_T != 0, oracle.initial_state(s) != 0)
+    if name == "p_continue = 1":
+        assert not np.any(S_T == 2)
+    if name == "p_continue = 0":
+        assert not np.any((states[1] == 1) & (oracle.initial_state(s) == 1))
