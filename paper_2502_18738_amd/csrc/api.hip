@@ -32,7 +32,7 @@ struct ScenLayout {
     int32_t pitch;
     int64_t PW;          // words per bit-plane
     int64_t max_tiles;   // flag capacity
-    size_t rec, th8, q8, g8, fuel, planes[2], flags[2], yhat, ckpt, tune, tign, tout;
+    size_t rec, th8, q8, g8, fuel, init, planes[2], flags[2], yhat, ckpt, tune, tign, tout;
 };
 
 struct Layout {
@@ -94,6 +94,7 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         s.th8 = take(32 * (size_t)cells);
         s.q8 = take(32 * (size_t)cells);
         s.fuel = take(4 * (size_t)s.PW);
+        s.init = take(4 * (size_t)s.PW);
         s.planes[0] = take(8 * (size_t)s.PW);
         s.planes[1] = take(8 * (size_t)s.PW);
         s.flags[0] = take((size_t)s.max_tiles);
@@ -334,7 +335,9 @@ int reset_state(sim_handle* h) {
     h->q_dirty = true;   // every run from a reset rebuilds the propagation table
     int rc = h->hip(fs::launch_init_state(h->st, h->d_jobs(),
                                           reinterpret_cast<const int32_t*>(h->ws + h->L.ib0),
-                                          h->n, h->ib0.back()), "init state");
+                                          h->n, h->ib0.back(),
+                                          reinterpret_cast<const int64_t*>(h->ws + h->L.cell0),
+                                          h->L.total_cells, h->calib()), "init state");
     if (rc) return rc;
     rc = refresh_worklist(h, false);   // init_state wrote both buffers
     if (rc) return rc;
@@ -449,7 +452,7 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
         J.rec = reinterpret_cast<const float4*>(h->ws + s.rec);
         J.th8 = reinterpret_cast<const float*>(h->ws + s.th8);
         J.q8 = reinterpret_cast<float*>(h->ws + s.q8);
-        J.ign = d.f.init_burning;
+        J.init = reinterpret_cast<const uint32_t*>(h->ws + s.init);
         J.g8 = h->calib() ? reinterpret_cast<float*>(h->ws + s.g8) : nullptr;
         J.fuel = reinterpret_cast<const uint32_t*>(h->ws + s.fuel);
         J.planes[0] = reinterpret_cast<uint32_t*>(h->ws + s.planes[0]);
@@ -479,6 +482,11 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
     for (int i = 0; i < n && !rc; ++i)
         rc = h->hip(fs::launch_slopes(h->st, h->job[i], const_cast<float*>(h->job[i].th8),
                                       descs[i].f.slope_deg, h->d_err()), "slope table");
+    // keep the packed initial burning plane for every reset
+    for (int i = 0; i < n && !rc; ++i)
+        rc = h->hip(hipMemcpyAsync(const_cast<uint32_t*>(h->job[i].init), h->job[i].planes[0],
+                                   4 * (size_t)h->L.s[i].PW, hipMemcpyDeviceToDevice, h->st),
+                    "keep initial state");
     h->cell0.assign(1, 0);
     for (int i = 0; i < n; ++i) h->cell0.push_back(h->cell0.back() + (int64_t)descs[i].H * descs[i].W);
     for (int i = 0; i < n; ++i) h->job[i].lam_off = h->cell0[i];
@@ -487,7 +495,7 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
                          "upload cell offsets");
     h->ib0.assign(1, 0);
     for (int i = 0; i < n; ++i)
-        h->ib0.push_back(h->ib0.back() + descs[i].H * (int32_t)cdiv(32 * h->job[i].pitch, 256));
+        h->ib0.push_back(h->ib0.back() + (int32_t)cdiv(h->L.s[i].PW, 256));
     if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.ib0, h->ib0.data(), sizeof(int32_t) * (n + 1),
                                         hipMemcpyHostToDevice, h->st), "upload reset blocks");
     if (!rc && h->calib()) {

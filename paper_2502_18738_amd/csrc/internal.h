@@ -43,7 +43,7 @@ struct DevScen {
     const float* th8;          // slope (Eq. 1, degrees) toward each of the 8 neighbours
     float* q8;                 // f_p(p_propagate) of each of the 8 incoming edges (per run)
     float* g8;                 // F e^z of each incoming edge (calibration) or nullptr
-    const uint8_t* ign;        // caller's initial burning cells (H*W, non-zero = burning)
+    const uint32_t* init;      // initial burning bit-plane (H * pitch words, packed at set-up)
     const uint32_t* fuel;      // fuel bit-plane
     uint32_t* planes[2];       // ping-pong state buffers
     uint8_t* flags[2];         // per-tile flags, per parity
@@ -120,10 +120,11 @@ hipError_t launch_overlap(hipStream_t st, const DevScen& job, int32_t parity, co
 hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
                          int64_t total_cells);
 // State of every scenario back to its initial burning cells (both ping-pong
-// buffers, accumulator, time maps); d_ib0 = n + 1 prefix sums of the blocks
-// per scenario, H * ceil(32 pitch / 256).
+// buffers; with maps, also the accumulator and time maps); d_ib0 = n + 1
+// prefix sums of the blocks per scenario, ceil(H * pitch / 256).
 hipError_t launch_init_state(hipStream_t st, const DevScen* d_jobs, const int32_t* d_ib0,
-                             int32_t n, int32_t nblocks);
+                             int32_t n, int32_t nblocks, const int64_t* d_cell0,
+                             int64_t total_cells, bool maps);
 // Time-map adjoint: one pass over every cell of every scenario; bl0 = n + 1
 // prefix sums of ceil(cells / 256) per scenario; writes gpart[block][4].
 hipError_t launch_adjoint_tmap(hipStream_t st, const DevScen* d_jobs, const int32_t* d_bl0,

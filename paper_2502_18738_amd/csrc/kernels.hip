@@ -744,15 +744,27 @@ k_slopes(DevScen J, float* __restrict__ th8, const float* __restrict__ slope9,
 // for every cell of every scenario; one flat grid, blocks mapped to scenarios
 // through the prefix sums of their cell counts.
 __global__ void __launch_bounds__(256)
-k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, int32_t n) {
-    const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (gi >= cell0[n]) return;
-    int lo = 0, hi = n;   // scenario s with cell0[s] <= gi < cell0[s + 1]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (cell0[mid] <= gi) lo = mid; else hi = mid;
+k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, int32_t n,
+         int64_t nvb) {
+    // a fixed grid walks the 256-cell segments; the scenario of a segment's
+    // first cell is found once per work-group, and a thread moves on to the
+    // next scenario(s) if its cell lies past the first one's end
+    int lo = 0;   // scenario s with cell0[s] <= g0 < cell0[s + 1]; g0 only grows
+    {
+        const int64_t g0 = (int64_t)blockIdx.x * 256;
+        int hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cell0[mid] <= g0) lo = mid; else hi = mid;
+        }
     }
-    const int s = lo;
+    for (int64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+    const int64_t g0 = vb * 256;
+    while (lo < n - 1 && g0 >= cell0[lo + 1]) ++lo;
+    const int64_t gi = g0 + threadIdx.x;
+    if (gi >= cell0[n]) continue;
+    int s = lo;
+    while (gi >= cell0[s + 1]) ++s;
     const DevScen& J = jobs[s];
     const int64_t j = gi - cell0[s];
     const float4 rec = J.rec[j];
@@ -775,6 +787,7 @@ k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, in
         float4* og = reinterpret_cast<float4*>(J.g8 + j * 8);
         og[0] = make_float4(g[0], g[1], g[2], g[3]);
         og[1] = make_float4(g[4], g[5], g[6], g[7]);
+    }
     }
 }
 
@@ -938,44 +951,64 @@ k_prologue(int32_t H, int32_t W, int32_t pitch, const float* __restrict__ p_veg,
 }
 
 __global__ void __launch_bounds__(256)
-k_init_state(const DevScen* __restrict__ jobs, const int32_t* __restrict__ ib0, int32_t n) {
-    const int b = blockIdx.x;
-    int lo = 0, hi = n;   // scenario s with ib0[s] <= b < ib0[s + 1]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (ib0[mid] <= b) lo = mid; else hi = mid;
-    }
-    const DevScen& J = jobs[lo];
-    const int H = J.H, W = J.W, pitch = J.pitch;
-    const uint8_t* ign = J.ign;
-    uint32_t* planes = J.planes[0];
-    uint32_t* planes2 = J.planes[1];
-    float* yhat = J.yhat;
-    int32_t* tign = J.tign;
-    int32_t* tout = J.tout;
-    const int bx = (pitch * 32 + 255) / 256;
-    const int local = b - ib0[lo];
-    const int r = local / bx;
-    const int c = (local - r * bx) * 256 + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    bool burning = false;
-    if (c < W) {
-        const int64_t j = (int64_t)r * W + c;
-        burning = ign[j] != 0;
-        if (yhat) yhat[j] = burning ? 1.f : 0.f;
-        if (tign) tign[j] = burning ? 0 : INT_MAX;
-        if (tout) tout[j] = INT_MAX;
-    }
-    const unsigned long long mb = __ballot(burning);
-    const int wbase = ((local - r * bx) * 256 + (threadIdx.x & ~63)) >> 5;
-    const int64_t PW = (int64_t)H * pitch;
-    if (lane == 0 || lane == 32) {
-        const int w = wbase + (lane >> 5);
-        if (w < pitch) {
-            const int64_t o = (int64_t)r * pitch + w;
-            planes[o] = planes2[o] = (uint32_t)(mb >> lane);
-            planes[PW + o] = planes2[PW + o] = 0u;
+k_init_state(const DevScen* __restrict__ jobs, const int32_t* __restrict__ ib0, int32_t n,
+             int32_t nblocks) {
+    // one thread per 32-cell word: both ping-pong buffers get the initial
+    // burning plane (packed once at set-up) and an empty burned plane
+    int lo = 0;   // scenario s with ib0[s] <= b < ib0[s + 1]; b only grows
+    {
+        int hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (ib0[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
         }
+    }
+    for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        while (b >= ib0[lo + 1]) ++lo;
+        const DevScen& J = jobs[lo];
+        const int64_t PW = (int64_t)J.H * J.pitch;
+        const int64_t o = (int64_t)(b - ib0[lo]) * 256 + threadIdx.x;
+        if (o < PW) {
+            const uint32_t w = gmem(J.init)[o];
+            FS_GLOBAL uint32_t* p0 = gmem(J.planes[0]);
+            FS_GLOBAL uint32_t* p1 = gmem(J.planes[1]);
+            p0[o] = w;
+            p1[o] = w;
+            p0[PW + o] = 0u;
+            p1[PW + o] = 0u;
+        }
+    }
+}
+
+// Calibration maps at a reset, one thread per cell: accumulator 1 on the
+// initial burning cells (a constant) and 0 elsewhere, ignition step 0 or
+// never, burn-out step never.
+__global__ void __launch_bounds__(256)
+k_init_maps(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, int32_t n,
+            int64_t nvb) {
+    int lo = 0;
+    {
+        const int64_t g0 = (int64_t)blockIdx.x * 256;
+        int hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cell0[mid] <= g0) lo = mid; else hi = mid;
+        }
+    }
+    for (int64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const int64_t g0 = vb * 256;
+        while (lo < n - 1 && g0 >= cell0[lo + 1]) ++lo;
+        const int64_t gi = g0 + threadIdx.x;
+        if (gi >= cell0[n]) continue;
+        int s = lo;
+        while (gi >= cell0[s + 1]) ++s;
+        const DevScen& J = jobs[s];
+        const int64_t j = gi - cell0[s];
+        const int r = (int)(j / J.W), c = (int)(j - (int64_t)r * J.W);
+        const bool burning = (gmem(J.init)[(int64_t)r * J.pitch + (c >> 5)] >> (c & 31)) & 1u;
+        gmem(J.yhat)[j] = burning ? 1.f : 0.f;
+        gmem(J.tign)[j] = burning ? 0 : INT_MAX;
+        gmem(J.tout)[j] = INT_MAX;
     }
 }
 
@@ -986,13 +1019,21 @@ k_init_state(const DevScen* __restrict__ jobs, const int32_t* __restrict__ ib0, 
 // gpart[block] receives the block's FP64 sum in a fixed order.
 __global__ void __launch_bounds__(256)
 k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0, int32_t n,
-               const float* __restrict__ lam, Rings rings, double* __restrict__ gpart) {
-    const int b = blockIdx.x;
-    int lo = 0, hi = n;   // scenario s with bl0[s] <= b < bl0[s + 1]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (bl0[mid] <= b) lo = mid; else hi = mid;
+               const float* __restrict__ lam, Rings rings, double* __restrict__ gpart,
+               int32_t nblocks) {
+    __shared__ double sh[4][256];
+    // a fixed grid walks the nblocks segments of 256 cells; each segment's
+    // partial sums go to its own slot, so the reduction order is fixed
+    int lo = 0;   // scenario s with bl0[s] <= b < bl0[s + 1]; b only grows
+    {
+        int hi = n;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bl0[mid] <= (int)blockIdx.x) lo = mid; else hi = mid;
+        }
     }
+    for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    while (b >= bl0[lo + 1]) ++lo;
     const DevScen& J = jobs[lo];
     const int64_t j = (int64_t)(b - bl0[lo]) * 256 + threadIdx.x;
     double g[4] = {0.0, 0.0, 0.0, 0.0};
@@ -1027,7 +1068,6 @@ k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0
             for (int m = 0; m < 4; ++m) g[m] = (double)(lj * gl[m]);
         }
     }
-    __shared__ double sh[4][256];
 #pragma unroll
     for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] = g[m];
     __syncthreads();
@@ -1037,6 +1077,8 @@ k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0
         __syncthreads();
     }
     if (threadIdx.x < 4) gpart[(int64_t)b * 4 + threadIdx.x] = sh[threadIdx.x][0];
+    __syncthreads();   // sh is reused by the next segment
+    }
 }
 
 __global__ void __launch_bounds__(256)
@@ -1470,15 +1512,23 @@ hipError_t launch_arrival(hipStream_t st, const DevScen* d_jobs, const DevScen& 
 hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
                          int64_t total_cells) {
     if (total_cells <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_qtable, dim3((unsigned)((total_cells + 255) / 256)), dim3(256), 0, st,
-                       d_jobs, d_cell0, n);
+    const int64_t nvb = (total_cells + 255) / 256;
+    hipLaunchKernelGGL(k_qtable, dim3((unsigned)std::min<int64_t>(nvb, 16384)), dim3(256), 0, st,
+                       d_jobs, d_cell0, n, nvb);
     return hipGetLastError();
 }
 
 hipError_t launch_init_state(hipStream_t st, const DevScen* d_jobs, const int32_t* d_ib0,
-                             int32_t n, int32_t nblocks) {
-    if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_init_state, dim3(nblocks), dim3(256), 0, st, d_jobs, d_ib0, n);
+                             int32_t n, int32_t nblocks, const int64_t* d_cell0,
+                             int64_t total_cells, bool maps) {
+    if (nblocks > 0)
+        hipLaunchKernelGGL(k_init_state, dim3(std::min(nblocks, 16384)), dim3(256), 0, st,
+                           d_jobs, d_ib0, n, nblocks);
+    if (maps && total_cells > 0) {
+        const int64_t nvb = (total_cells + 255) / 256;
+        hipLaunchKernelGGL(k_init_maps, dim3((unsigned)std::min<int64_t>(nvb, 16384)), dim3(256),
+                           0, st, d_jobs, d_cell0, n, nvb);
+    }
     return hipGetLastError();
 }
 
@@ -1504,8 +1554,8 @@ hipError_t launch_adjoint_tmap(hipStream_t st, const DevScen* d_jobs, const int3
                                int32_t n, int32_t nblocks, const float* lam, Rings rings,
                                double* gpart) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adjoint_tmap, dim3(nblocks), dim3(256), 0, st, d_jobs, d_bl0, n, lam,
-                       rings, gpart);
+    hipLaunchKernelGGL(k_adjoint_tmap, dim3(std::min(nblocks, 16384)), dim3(256), 0, st, d_jobs,
+                       d_bl0, n, lam, rings, gpart, nblocks);
     return hipGetLastError();
 }
 
