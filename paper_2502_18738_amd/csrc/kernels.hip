@@ -746,9 +746,31 @@ k_slopes(DevScen J, float* __restrict__ th8, const float* __restrict__ slope9,
 __global__ void __launch_bounds__(256)
 k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, int32_t n,
          int64_t nvb) {
+    // one cell: q8 (and g8 in calibration handles) of its 8 incoming edges
+    auto cell = [&](const DevScen& J, int64_t j) {
+        const float4 rec = load_f4(J.rec, j);
+        const float4 ta = load_f4(J.th8, 2 * j), tb = load_f4(J.th8, 2 * j + 1);
+        const float th[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
+        float q[8], g[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            int dr, dc;
+            slot_dir(m, dr, dc);
+            const Edge e = edge_terms(J, rec, th[m], dr, dc);
+            q[m] = e.q;
+            g[m] = rec.x * e.ez;
+        }
+        FS_GLOBAL fs_f4* o = (FS_GLOBAL fs_f4*)gmem(J.q8) + 2 * j;
+        o[0] = fs_f4{q[0], q[1], q[2], q[3]};
+        o[1] = fs_f4{q[4], q[5], q[6], q[7]};
+        if (J.g8) {
+            FS_GLOBAL fs_f4* og = (FS_GLOBAL fs_f4*)gmem(J.g8) + 2 * j;
+            og[0] = fs_f4{g[0], g[1], g[2], g[3]};
+            og[1] = fs_f4{g[4], g[5], g[6], g[7]};
+        }
+    };
     // a fixed grid walks the 256-cell segments; the scenario of a segment's
-    // first cell is found once per work-group, and a thread moves on to the
-    // next scenario(s) if its cell lies past the first one's end
+    // first cell is found by advancing from the previous segment's
     int lo = 0;   // scenario s with cell0[s] <= g0 < cell0[s + 1]; g0 only grows
     {
         const int64_t g0 = (int64_t)blockIdx.x * 256;
@@ -758,36 +780,20 @@ k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, in
             if (cell0[mid] <= g0) lo = mid; else hi = mid;
         }
     }
+    const int64_t total = cell0[n];
     for (int64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-    const int64_t g0 = vb * 256;
-    while (lo < n - 1 && g0 >= cell0[lo + 1]) ++lo;
-    const int64_t gi = g0 + threadIdx.x;
-    if (gi >= cell0[n]) continue;
-    int s = lo;
-    while (gi >= cell0[s + 1]) ++s;
-    const DevScen& J = jobs[s];
-    const int64_t j = gi - cell0[s];
-    const float4 rec = J.rec[j];
-    const float4* tv = reinterpret_cast<const float4*>(J.th8 + j * 8);
-    const float4 ta = tv[0], tb = tv[1];
-    const float th[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
-    float q[8], g[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        int dr, dc;
-        slot_dir(m, dr, dc);
-        const Edge e = edge_terms(J, rec, th[m], dr, dc);
-        q[m] = e.q;
-        g[m] = rec.x * e.ez;
-    }
-    float4* o = reinterpret_cast<float4*>(J.q8 + j * 8);
-    o[0] = make_float4(q[0], q[1], q[2], q[3]);
-    o[1] = make_float4(q[4], q[5], q[6], q[7]);
-    if (J.g8) {
-        float4* og = reinterpret_cast<float4*>(J.g8 + j * 8);
-        og[0] = make_float4(g[0], g[1], g[2], g[3]);
-        og[1] = make_float4(g[4], g[5], g[6], g[7]);
-    }
+        const int64_t g0 = vb * 256;
+        while (lo < n - 1 && g0 >= cell0[lo + 1]) ++lo;
+        const int64_t gi = g0 + threadIdx.x;
+        if (g0 + 256 <= cell0[lo + 1]) {
+            // the whole segment lies in scenario lo: its descriptor is uniform
+            const int su = __builtin_amdgcn_readfirstlane(lo);
+            cell(jobs[su], gi - cell0[su]);
+        } else if (gi < total) {
+            int s = lo;   // the segment straddles scenarios
+            while (gi >= cell0[s + 1]) ++s;
+            cell(jobs[s], gi - cell0[s]);
+        }
     }
 }
 
