@@ -56,9 +56,15 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the library sources with comments and blank space removed, so
+    that committed counter runs stay matched to the code they measured."""
+    import re
+    tok = re.compile(r'"(?:\\.|[^"\\])*"|//[^\n]*|/\*.*?\*/', re.S)
     h = hashlib.sha256()
     for f in ("kernels.hip", "api.hip", "internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_2502_18738_amd", "csrc", f), "rb").read())
+        src = open(os.path.join(ROOT, "paper_2502_18738_amd", "csrc", f)).read()
+        code = tok.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", src)
+        h.update(" ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -6,15 +6,16 @@
 // cells per bitwise instruction, so finding the cells that need a Bernoulli
 // trial (burning cells, and burnable cells with fuel next to a burning cell,
 // Sec. 2.2 transition rules) costs a handful of bit operations per 32 cells.
-// Only those trial cells touch the per-cell fields: the fire front is a thin
-// ring, so per-edge transcendental work (Eq. 1-5) and field gathers scale with
-// the front, not with the grid.  Trials are compacted into an LDS list by a
-// work-group prefix sum and dealt round-robin to the work-group's lanes, so one busy
-// word does not serialise a wavefront.
+// The per-edge terms of Eq. 1-5 are evaluated once per run for every edge by
+// `k_qtable` (parameters and fields do not change within a run); a step only
+// gathers the 32-byte table row of each ignition-trial cell, so the step's
+// memory traffic scales with the fire front, not with the grid.  Trials are
+// compacted into an LDS list by a work-group prefix sum and dealt to the
+// work-group's lanes, so one busy word does not serialise a wavefront.
 //
 // Compiled with -ffp-contract=off: every FP32 operation rounds as written, so
-// the forward and adjoint instantiations compute bit-identical p_ignite and
-// take identical ignition decisions when the adjoint recomputes a segment.
+// every kernel that evaluates Eq. 2-5 and 9 produces the same bits, and the
+// adjoint recompute takes exactly the forward's ignition decisions.
 #include "internal.h"
 
 #include <math.h>
