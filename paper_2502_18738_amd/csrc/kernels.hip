@@ -273,6 +273,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     constexpr int WPT = (NW + NT - 1) / NT;
     constexpr int NWAVE = NT / 64;
     constexpr int LCAP = NW * 32;  // worst case: every cell of the region has a trial
+    static_assert(LCAP <= 32768, "entries carry an ignition flag in bit 15");
     static_assert(NW * 32 < 65536, "trial list entries are 16-bit");
     static_assert(KM <= TR && KM <= 32, "halo deeper than a tile");
 
@@ -281,8 +282,8 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     // The burned plane of a word lives in its owner thread's registers.
     __shared__ uint32_t sB[2][NW], sU[NW];
     __shared__ uint16_t sL[LCAP];
-    // words holding a trial this step: (word index, continue mask, ignition
-    // mask, offsets of their first list entries: continue | ignition << 16)
+    // words holding a trial this step: (word index, trial mask, ignition
+    // mask, offset of the word's first list entry)
     __shared__ uint4 sWL[NW];
     // per word, which of the 8 neighbour slots of each of its 32 cells burn
     // (one mask per slot), written for words with ignition trials
@@ -425,7 +426,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         // trial masks of this thread's words: continue trials (burning cells)
         // and ignition trials (burnable cells with fuel and a burning neighbour)
         uint32_t mc[WPT], mi[WPT];
-        int cnt = 0;  // continue count | ignition count << 16
+        int cnt = 0;  // trials of this thread's words
         int nne = 0;  // words of this thread with a trial
 #pragma unroll
         for (int i = 0; i < WPT; ++i) {
@@ -460,7 +461,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     bprev[i] = mid;
                     mc[i] = mid;
                     mi[i] = nbm & ~mid & ~dreg[i] & sU[w];
-                    cnt += __popc(mc[i]) | (__popc(mi[i]) << 16);
+                    cnt += __popc(mc[i] | mi[i]);
                     nne += (mc[i] | mi[i]) != 0u;
                     nR[w] = 0;
                     if (mi[i]) {
@@ -472,22 +473,22 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         }
         int tot, pre_w, tot_w;
         const int off = block_exscan2<NWAVE>(cnt, nne, sWave, &tot, &pre_w, &tot_w);
-        const int tot_c = tot & 0xFFFF, tot_i = tot >> 16;
+        const int ntr = tot;
 
-        // compacted trial list, continue entries first, then ignition entries:
-        // the words with trials are listed first, then 32 lanes per listed
-        // word place its set bits (rank = popcount below the bit), so a busy
-        // word costs no more than a quiet one
+        // compacted trial list in word order, bit 15 of an entry marking an
+        // ignition trial (else a continue trial): the words with trials are
+        // listed first, then 32 lanes per listed word place its set bits
+        // (rank = popcount below the bit), so a busy word costs no more than a
+        // quiet one
         {
-            int oc = off & 0xFFFF, oi = off >> 16, k = pre_w;
+            int oc = off, k = pre_w;
 #pragma unroll
             for (int i = 0; i < WPT; ++i) {
-                if (mc[i] | mi[i]) {
-                    sWL[k] = make_uint4((uint32_t)(tid + i * NT), mc[i], mi[i],
-                                        (uint32_t)oc | ((uint32_t)oi << 16));
+                const uint32_t mm = mc[i] | mi[i];
+                if (mm) {
+                    sWL[k] = make_uint4((uint32_t)(tid + i * NT), mm, mi[i], (uint32_t)oc);
                     ++k;
-                    oc += __popc(mc[i]);
-                    oi += __popc(mi[i]);
+                    oc += __popc(mm);
                 }
             }
         }
@@ -496,13 +497,12 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             const int b = x & 31;
             const uint32_t bm = 1u << b;
             const uint4 wl = sWL[x >> 5];
-            const uint16_t e = (uint16_t)(wl.x * 32 + b);
-            if (wl.y & bm) sL[(wl.w & 0xFFFFu) + __popc(wl.y & (bm - 1u))] = e;
-            else if (wl.z & bm) sL[tot_c + (wl.w >> 16) + __popc(wl.z & (bm - 1u))] = e;
+            if (wl.y & bm)
+                sL[wl.w + __popc(wl.y & (bm - 1u))] =
+                    (uint16_t)((wl.x * 32 + b) | ((wl.z & bm) ? 0x8000u : 0u));
         }
         __syncthreads();
 
-        const int ntr = tot_c + tot_i;
         {
             // p_ignite of an ignition trial is Eq. 9 over the q8 entries of its
             // burning neighbour slots (the Eq. 2-5 work was done for every edge
@@ -523,7 +523,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             // listed cell lies inside the grid)
             const int64_t jbase = (int64_t)r0 * J.W + (int64_t)w0 * 32;
             for (int k0 = 0; k0 < ntr; k0 += R * NT) {
-                int ent[R];
+                int ent[R], ign[R];
                 fs_f4 qa[R], qb[R];
                 fs_f4 ga[R], gb[R], ta[R], tb[R];   // adjoint only
                 float4 rc[R];
@@ -532,14 +532,16 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 for (int r = 0; r < R; ++r) {
                     if (k0 + r * NT >= ntr) break;   // uniform: no lane has trial r
                     const int k = k0 + r * NT + tid;
-                    ent[r] = k < ntr ? (int)sL[k] : -1;
+                    ent[r] = k < ntr ? (int)sL[k] : 0;
+                    ign[r] = (ent[r] >> 15) & 1;
+                    ent[r] &= 0x7FFF;
                     qa[r] = qb[r] = (fs_f4)(0.f);
                     if constexpr (ADJ) {
                         ga[r] = gb[r] = ta[r] = tb[r] = (fs_f4)(0.f);
                         rc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
                         lj[r] = 0.f;
                     }
-                    if (k >= tot_c && k < ntr) {
+                    if (k < ntr && ign[r]) {
                         const int w = ent[r] >> 5, bit = ent[r] & 31;
                         const int lr = w / RC, lc = w - (w / RC) * RC;
                         const int64_t j = jbase + (lr * J.W + lc * 32 + bit);
@@ -569,7 +571,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     uint32_t rw0, rw1;
                     philox_w01((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, scen,
                                k0s, k1s, rw0, rw1);
-                    if (k < tot_c) {  // burning: continue trial
+                    if (!ign[r]) {  // burning: continue trial
                         if (u24(rw1) < J.p_continue) {
                             atomicOr(&nR[w], 1u << bit);
                         } else if (interior && J.tout) {
