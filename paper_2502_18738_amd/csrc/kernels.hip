@@ -1,7 +1,9 @@
 // kernels.hip -- gfx950 kernels of the wildfire cellular automaton.
 //
 // The hot path is `k_step`: one work-group advances one tile of one scenario
-// by up to KM steps entirely in LDS (temporal blocking).  The state is two
+// by up to KM steps entirely in LDS (temporal blocking); step s of a K-step
+// launch only tries the cells within K - s cells of the tile, the ones that
+// can still reach it before the launch ends.  The state is two
 // bit-planes (burning, burned); a 64-lane wavefront treats 64 words = 2048
 // cells per bitwise instruction, so finding the cells that need a Bernoulli
 // trial (burning cells, and burnable cells with fuel next to a burning cell,
@@ -348,7 +350,8 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     const FS_GLOBAL uint32_t* fuel = gmem(J.fuel);
     const FS_GLOBAL float* q8g = gmem(J.q8);
 
-    const int kj = min(ksteps, J.t_end - (J.t_base + t_off));
+    // steps of this launch for this job; never more than the halo covers
+    const int kj = min(min(ksteps, KM), J.t_end - (J.t_base + t_off));
     if (kj <= 0) continue;
 
     // ---- skip a tile when no tile within reach holds a burning cell
@@ -419,7 +422,13 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     for (int s = 1; s <= kj; ++s) {
         __syncthreads();
         const int t = J.t_base + t_off + s;
-        const int lo = s, hi = RR - s;
+        // cells still needed: rows and halo-word bits within kj - s cells of
+        // the tile (they are also the ones whose inputs are still valid; trials
+        // farther out could not reach the tile before the launch ends)
+        const int need_d = kj - s;
+        const int lo = KM - need_d, hi = RR - lo;
+        const uint32_t keepL = need_d == 0 ? 0u : ~0u << (32 - need_d);
+        const uint32_t keepR = (1u << need_d) - 1u;
         const uint32_t* cB = sB[cur];
         uint32_t* nR = sB[cur ^ 1];
 
@@ -459,8 +468,9 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     // burned at t-1: burned before, or burning at t-2 and not at t-1
                     dreg[i] |= bprev[i] & ~mid;
                     bprev[i] = mid;
-                    mc[i] = mid;
-                    mi[i] = nbm & ~mid & ~dreg[i] & sU[w];
+                    const uint32_t keep = lc == 0 ? keepL : (lc == RC - 1 ? keepR : ~0u);
+                    mc[i] = mid & keep;
+                    mi[i] = nbm & ~mid & ~dreg[i] & sU[w] & keep;
                     cnt += __popc(mc[i] | mi[i]);
                     nne += (mc[i] | mi[i]) != 0u;
                     nR[w] = 0;
@@ -1700,7 +1710,7 @@ hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_
                        int32_t t_off, int32_t ksteps, int32_t skip, const float* lam,
                        Rings rings, Sched sched, int32_t grid, unsigned long long* d_stats) {
     const StepEntry* e = find_step(sh, adj);
-    if (!e) return hipErrorInvalidValue;
+    if (!e || ksteps > sh.km) return hipErrorInvalidValue;
     if (ntiles <= 0) return hipSuccess;
     int nb = ntiles;
     if (sched.in) {
