@@ -483,7 +483,14 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         }
         int tot, pre_w, tot_w;
         const int off = block_exscan2<NWAVE>(cnt, nne, sWave, &tot, &pre_w, &tot_w);
-        const int ntr = tot;
+        // (a scalar: the branches on it below are uniform)
+        const int ntr = __builtin_amdgcn_readfirstlane(tot);
+        if (ntr == 0) {
+            // no trial within reach of the tile: no cell of the band burns or
+            // can ignite, so the band stays as it is for the rest of the launch
+            cur ^= 1;
+            break;
+        }
 
         // compacted trial list in word order, bit 15 of an entry marking an
         // ignition trial (else a continue trial): the words with trials are
