@@ -347,7 +347,7 @@ def leg_cpu(args, s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--legs", default="main,plain,calib,batched,paper,cpu")
     ap.add_argument("--exec", default=None, metavar="TR,TC,DEPTH,SKIP[,THREADS]",

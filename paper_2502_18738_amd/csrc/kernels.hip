@@ -494,9 +494,9 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
 
         // compacted trial list in word order, bit 15 of an entry marking an
         // ignition trial (else a continue trial): the words with trials are
-        // listed first, then 32 lanes per listed word place its set bits
-        // (rank = popcount below the bit), so a busy word costs no more than a
-        // quiet one
+        // listed first, then 8 lanes per listed word place its set bits, 4
+        // bits each (rank = popcount below the bit), so a busy word costs
+        // little more than a quiet one
         {
             int oc = off, k = pre_w;
 #pragma unroll
@@ -510,13 +510,23 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             }
         }
         __syncthreads();
-        for (int x = tid; x < tot_w * 32; x += NT) {
-            const int b = x & 31;
-            const uint32_t bm = 1u << b;
-            const uint4 wl = sWL[x >> 5];
-            if (wl.y & bm)
-                sL[wl.w + __popc(wl.y & (bm - 1u))] =
-                    (uint16_t)((wl.x * 32 + b) | ((wl.z & bm) ? 0x8000u : 0u));
+        for (int x = tid; x < tot_w * 8; x += NT) {
+            // lane x & 7 of a listed word places the trials among its bits
+            // 4 (x & 7) .. 4 (x & 7) + 3
+            const uint4 wl = sWL[x >> 3];
+            const int b0 = (x & 7) * 4;
+            const uint32_t m = (wl.y >> b0) & 15u;
+            if (m) {
+                int pos = wl.w + __popc(wl.y & ((1u << b0) - 1u));
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if ((m >> q) & 1u) {
+                        const int b = b0 + q;
+                        sL[pos] = (uint16_t)((wl.x * 32 + b) | (((wl.z >> b) & 1u) ? 0x8000u : 0u));
+                        ++pos;
+                    }
+                }
+            }
         }
         __syncthreads();
 
