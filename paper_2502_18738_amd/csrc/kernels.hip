@@ -151,6 +151,15 @@ __device__ __forceinline__ bool attached(const Rings& rg, int t) {
     return false;
 }
 
+// Value of lane - 1 / lane + 1 of the wavefront (0 at lane 0 / lane 63), by
+// DPP whole-wavefront shifts.
+__device__ __forceinline__ uint32_t lane_prev(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x138, 0xF, 0xF, true);  // wave_shr:1
+}
+__device__ __forceinline__ uint32_t lane_next(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x130, 0xF, 0xF, true);  // wave_shl:1
+}
+
 // Inclusive prefix sum over the 64 lanes of a wavefront with DPP lane moves
 // (shifts inside 16-lane rows, then the row-15 and row-31 broadcasts), so the
 // scan costs six register-to-register moves instead of LDS permutes.  Every
@@ -443,21 +452,36 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             mc[i] = mi[i] = 0;
             if (w < NW) {
                 const int lr = w / RC, lc = w - (w / RC) * RC;
+                uint32_t up = 0, mid = 0, dn = 0;
+                uint32_t upL = 0, midL = 0, dnL = 0, upR = 0, midR = 0, dnR = 0;
+                if constexpr (64 % RC == 0) {
+                    // rows never straddle a wavefront: the left and right
+                    // neighbour words are held by lanes -1 and +1 (every lane
+                    // of the row's wavefront reads its words first)
+                    if (lr > 0) up = cB[(lr - 1) * RC + lc];
+                    mid = cB[lr * RC + lc];
+                    if (lr < RR - 1) dn = cB[(lr + 1) * RC + lc];
+                    const uint32_t uL = lane_prev(up), mL = lane_prev(mid), dL = lane_prev(dn);
+                    const uint32_t uR = lane_next(up), mR = lane_next(mid), dR = lane_next(dn);
+                    if (lc > 0) { upL = uL; midL = mL; dnL = dL; }
+                    if (lc < RC - 1) { upR = uR; midR = mR; dnR = dR; }
+                }
                 if (lr >= lo && lr < hi) {
                     // burning-neighbour masks per slot (slot order of slot_dir):
                     // bit b of slot (dr, dc) = cell (lr + dr, 32 lc + b + dc) burns
-                    const int a = (lr - 1) * RC, b = lr * RC, c = (lr + 1) * RC;
-                    const uint32_t up = cB[a + lc], mid = cB[b + lc], dn = cB[c + lc];
-                    uint32_t upL = 0, midL = 0, dnL = 0, upR = 0, midR = 0, dnR = 0;
-                    if (lc > 0) {
-                        upL = cB[a + lc - 1];
-                        midL = cB[b + lc - 1];
-                        dnL = cB[c + lc - 1];
-                    }
-                    if (lc < RC - 1) {
-                        upR = cB[a + lc + 1];
-                        midR = cB[b + lc + 1];
-                        dnR = cB[c + lc + 1];
+                    if constexpr (64 % RC != 0) {
+                        const int a = (lr - 1) * RC, b = lr * RC, c = (lr + 1) * RC;
+                        up = cB[a + lc]; mid = cB[b + lc]; dn = cB[c + lc];
+                        if (lc > 0) {
+                            upL = cB[a + lc - 1];
+                            midL = cB[b + lc - 1];
+                            dnL = cB[c + lc - 1];
+                        }
+                        if (lc < RC - 1) {
+                            upR = cB[a + lc + 1];
+                            midR = cB[b + lc + 1];
+                            dnR = cB[c + lc + 1];
+                        }
                     }
                     const uint32_t n0 = (up << 1) | (upL >> 31), n1 = up,
                                    n2 = (up >> 1) | (upR << 31);

@@ -144,6 +144,8 @@ SHAPES = [
     dict(tile_rows=32, tile_words=4, depth=20, skip=2),
     dict(tile_rows=32, tile_words=4, depth=8, skip=1, threads=256),
     dict(tile_rows=32, tile_words=2, depth=32, skip=0, threads=512),
+    dict(tile_rows=32, tile_words=2, depth=32, skip=1, threads=256),
+    dict(tile_rows=8, tile_words=2, depth=8, skip=1),
 ]
 
 
