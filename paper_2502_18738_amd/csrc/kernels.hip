@@ -274,8 +274,15 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 
 // --------------------------------------------------------------- main step
 
+// 256-lane shapes serve many busy tiles at once (ensembles, calibration): they
+// aim at 96 registers so that 5 wavefronts share a SIMD, and they keep no
+// per-word slot masks in LDS (see SN below), so that more work-groups fit a CU.
+// Shapes with several words per lane cannot reach that target; the compiler
+// then settles on the occupancy it can reach (its warning is silenced).
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wpass-failed"
 template <int TR, int TC, int KM, bool ADJ, int NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 1 : 5)))
 k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, int32_t ntiles,
        int32_t parity, int32_t t_off, int32_t ksteps, int32_t skip,
        const float* __restrict__ lam, Rings rings, Sched sched,
@@ -297,8 +304,11 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     // mask, offset of the word's first list entry)
     __shared__ uint4 sWL[NW];
     // per word, which of the 8 neighbour slots of each of its 32 cells burn
-    // (one mask per slot), written for words with ignition trials
-    __shared__ uint4 sN[NW][2];
+    // (one mask per slot), written for words with ignition trials by the
+    // 512-lane shapes; the others rebuild an ignition trial's masks from the
+    // state plane (nine LDS reads instead of two, a third less LDS)
+    constexpr bool SN = NT >= 512;
+    __shared__ uint4 sN[SN ? NW : 1][2];
     __shared__ int sWave[2 * NWAVE];
     __shared__ int sFlag;
     __shared__ double sG[ADJ ? NWAVE * 4 : 1];
@@ -498,9 +508,11 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     cnt += __popc(mc[i] | mi[i]);
                     nne += (mc[i] | mi[i]) != 0u;
                     nR[w] = 0;
-                    if (mi[i]) {
-                        sN[w][0] = make_uint4(n0, n1, n2, n3);
-                        sN[w][1] = make_uint4(n4, n5, n6, n7);
+                    if constexpr (SN) {
+                        if (mi[i]) {
+                            sN[w][0] = make_uint4(n0, n1, n2, n3);
+                            sN[w][1] = make_uint4(n4, n5, n6, n7);
+                        }
                     }
                 }
             }
@@ -633,8 +645,37 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     }
                     const float qs[8] = {qa[r].x, qa[r].y, qa[r].z, qa[r].w,
                                          qb[r].x, qb[r].y, qb[r].z, qb[r].w};
-                    const uint4 na = sN[w][0], nb = sN[w][1];
-                    const uint32_t nm[8] = {na.x, na.y, na.z, na.w, nb.x, nb.y, nb.z, nb.w};
+                    uint32_t nm[8];
+                    if constexpr (SN) {
+                        const uint4 na = sN[w][0], nb = sN[w][1];
+                        nm[0] = na.x; nm[1] = na.y; nm[2] = na.z; nm[3] = na.w;
+                        nm[4] = nb.x; nm[5] = nb.y; nm[6] = nb.z; nm[7] = nb.w;
+                    } else {
+                        // the same masks as the mask phase, from S(t-1) (a
+                        // trial cell lies in rows 1 .. RR-2 of the region)
+                        const uint32_t* cB = sB[cur];
+                        const int a = (lr - 1) * RC, bq = lr * RC, c = (lr + 1) * RC;
+                        const uint32_t up = cB[a + lc], mid = cB[bq + lc], dn = cB[c + lc];
+                        uint32_t upL = 0, midL = 0, dnL = 0, upR = 0, midR = 0, dnR = 0;
+                        if (lc > 0) {
+                            upL = cB[a + lc - 1];
+                            midL = cB[bq + lc - 1];
+                            dnL = cB[c + lc - 1];
+                        }
+                        if (lc < RC - 1) {
+                            upR = cB[a + lc + 1];
+                            midR = cB[bq + lc + 1];
+                            dnR = cB[c + lc + 1];
+                        }
+                        nm[0] = (up << 1) | (upL >> 31);
+                        nm[1] = up;
+                        nm[2] = (up >> 1) | (upR << 31);
+                        nm[3] = (mid << 1) | (midL >> 31);
+                        nm[4] = (mid >> 1) | (midR << 31);
+                        nm[5] = (dn << 1) | (dnL >> 31);
+                        nm[6] = dn;
+                        nm[7] = (dn >> 1) | (dnR << 31);
+                    }
                     float q[8];
 #pragma unroll
                     for (int m = 0; m < 8; ++m) q[m] = ((nm[m] >> bit) & 1u) ? qs[m] : 0.f;
@@ -753,6 +794,8 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     }
     }  // work items
 }
+
+#pragma clang diagnostic pop
 
 // ------------------------------------------------- per-edge tables (Eq. 1-5)
 
