@@ -569,15 +569,16 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         {
             // p_ignite of an ignition trial is Eq. 9 over the q8 entries of its
             // burning neighbour slots (the Eq. 2-5 work was done for every edge
-            // at the start of the run).  Each lane takes up to 4 trials per pass
+            // at the start of the run).  Each lane takes up to R trials per pass
             // and issues all of their gathers before deciding.  The adjoint
             // recompute takes the same decisions from the same values and, for
             // the cells that ignite inside the tile at an attached step, adds
             // lambda_j * d p_ignite_j / d theta (Eq. 2-5 and 9 differentiated).
             // the adjoint also reads each interior trial's gradient rows with its
             // q8 row (one round trip per step), so it holds one trial per lane
-            // per pass (fewer registers, more resident waves; measured fastest)
-            constexpr int R = ADJ ? 1 : 4;
+            // per pass (fewer registers, more resident waves; measured fastest);
+            // the 256-lane shapes, held to 96 registers, take two
+            constexpr int R = ADJ ? 1 : (NT >= 512 ? 4 : 2);
             const bool att = ADJ && attached(rings, t);
             const FS_GLOBAL fs_f4* q8v = (const FS_GLOBAL fs_f4*)q8g;
             const FS_GLOBAL fs_f4* g8v = (const FS_GLOBAL fs_f4*)gmem(J.g8);
