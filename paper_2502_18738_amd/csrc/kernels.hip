@@ -577,8 +577,9 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             // the adjoint also reads each interior trial's gradient rows with its
             // q8 row (one round trip per step), so it holds one trial per lane
             // per pass (fewer registers, more resident waves; measured fastest);
-            // the 256-lane shapes, held to 96 registers, take two
-            constexpr int R = ADJ ? 1 : (NT >= 512 ? 4 : 2);
+            // so do the 512-lane shapes (a busy tile rarely has more trials
+            // than lanes), while the 256-lane shapes take two
+            constexpr int R = ADJ ? 1 : (NT >= 512 ? 1 : 2);
             const bool att = ADJ && attached(rings, t);
             const FS_GLOBAL fs_f4* q8v = (const FS_GLOBAL fs_f4*)q8g;
             const FS_GLOBAL fs_f4* g8v = (const FS_GLOBAL fs_f4*)gmem(J.g8);
