@@ -574,12 +574,10 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             // recompute takes the same decisions from the same values and, for
             // the cells that ignite inside the tile at an attached step, adds
             // lambda_j * d p_ignite_j / d theta (Eq. 2-5 and 9 differentiated).
-            // the adjoint also reads each interior trial's gradient rows with its
-            // q8 row (one round trip per step), so it holds one trial per lane
-            // per pass (fewer registers, more resident waves; measured fastest);
-            // so do the 512-lane shapes (a busy tile rarely has more trials
-            // than lanes), while the 256-lane shapes take two
-            constexpr int R = ADJ ? 1 : (NT >= 512 ? 1 : 2);
+            // one trial per lane per pass: a busy tile rarely has more trials
+            // than lanes, and fewer registers mean more resident wavefronts
+            // (2 and 4 trials per lane measured slower on every workload)
+            constexpr int R = 1;
             const bool att = ADJ && attached(rings, t);
             const FS_GLOBAL fs_f4* q8v = (const FS_GLOBAL fs_f4*)q8g;
             const FS_GLOBAL fs_f4* g8v = (const FS_GLOBAL fs_f4*)gmem(J.g8);
