@@ -1362,6 +1362,7 @@ k_loss_terms(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0
     const int b0 = box[0], b1 = box[1], c0 = box[2], c1 = box[3];
     const bool has_box = b1 >= b0;
     const double N = has_box ? (double)(b1 - b0 + 1) * (double)(c1 - c0 + 1) : 1.0;
+    const double invN = 1.0 / N;
     const int Hp = H / 4, Wp = W / 4;
     const double Np = (double)Hp * (double)Wp;
     double bce = 0.0, mse = 0.0;
@@ -1370,10 +1371,15 @@ k_loss_terms(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0
             const int64_t j = (int64_t)r * W + c;
             double lam = 0.0;
             if ((kind == 0 || kind == 1) && has_box && r >= b0 && r <= b1 && c >= c0 && c <= c1) {
-                const double z = (double)yhat[j], yy = (double)y[j];
-                const double sig = 1.0 / (1.0 + exp(-z));
-                bce += -(yy * log(sig) + (1.0 - yy) * log(1.0 - sig));
-                lam += (sig - yy) / N;
+                // BCE with logits per cell in FP32, -(y log s + (1 - y) log(1 - s))
+                // with s = sigmoid(z), written as softplus(z) - y z; its derivative
+                // is s - y.  The sums over cells are FP64.
+                const float z = yhat[j], yy = (float)y[j];
+                const float e = expf(-fabsf(z));
+                const float sp = fmaxf(z, 0.f) + log1pf(e);
+                const float sig = z >= 0.f ? 1.f / (1.f + e) : e / (1.f + e);
+                bce += (double)(sp - yy * z);
+                lam += (double)(sig - yy) * invN;
             }
             lambda[j] = (float)lam;
         }
