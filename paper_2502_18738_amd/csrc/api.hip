@@ -32,7 +32,7 @@ struct ScenLayout {
     int32_t pitch;
     int64_t PW;          // words per bit-plane
     int64_t max_tiles;   // flag capacity
-    size_t rec, th8, q8, g8, fuel, init, planes[2], flags[2], yhat, ckpt, tune, tign, tout;
+    size_t rec, th8, q8, fuel, init, planes[2], flags[2], yhat, ckpt, tune, tign, tout;
 };
 
 struct Layout {
@@ -99,11 +99,10 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         s.planes[1] = take(8 * (size_t)s.PW);
         s.flags[0] = take((size_t)s.max_tiles);
         s.flags[1] = take((size_t)s.max_tiles);
-        s.yhat = s.ckpt = s.tune = s.tign = s.tout = s.g8 = 0;
+        s.yhat = s.ckpt = s.tune = s.tign = s.tout = 0;
         if (!calib) s.tune = take(8 * (size_t)s.PW);   // state saved while autotuning
         if (calib) {
             s.yhat = take(4 * (size_t)cells);
-            s.g8 = take(32 * (size_t)cells);
             s.tign = take(4 * (size_t)cells);
             s.tout = take(4 * (size_t)cells);
             s.ckpt = take(8 * (size_t)s.PW * (size_t)L->nseg);
@@ -453,7 +452,6 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
         J.th8 = reinterpret_cast<const float*>(h->ws + s.th8);
         J.q8 = reinterpret_cast<float*>(h->ws + s.q8);
         J.init = reinterpret_cast<const uint32_t*>(h->ws + s.init);
-        J.g8 = h->calib() ? reinterpret_cast<float*>(h->ws + s.g8) : nullptr;
         J.fuel = reinterpret_cast<const uint32_t*>(h->ws + s.fuel);
         J.planes[0] = reinterpret_cast<uint32_t*>(h->ws + s.planes[0]);
         J.planes[1] = reinterpret_cast<uint32_t*>(h->ws + s.planes[1]);
@@ -928,7 +926,7 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
                       "zero gradient");
     fs::Rings rg = h->rings;
     rg.T = T;
-    // both adjoints read the q8 / g8 tables of the current parameters
+    // both adjoints read the q8 table of the current parameters
     if (int rc = ensure_qtable(h)) return rc;
     if (h->adj_method == 1) {
         auto* gp = reinterpret_cast<double*>(h->ws + h->L.gpart_tmap);

@@ -10,9 +10,6 @@
 //           neighbour slot into the cell for the current parameters (Eq. 2-5),
 //           rebuilt at the start of a run whenever parameters or the run
 //           changed.  Slot order: (dr, dc) row by row, centre skipped.
-//   g8      8 floats per cell (calibration handles only): F e^z of each edge,
-//           i.e. d x / d p_h of Eq. 2, written with q8; the adjoints build the
-//           remaining derivatives from it without transcendental functions.
 //   fuel    one bit per cell (F > 0), rows of `pitch` 32-bit words.
 //   planes  two ping-pong buffers; each holds the burning bit-plane followed
 //           by the burned bit-plane (2 * H * pitch words): 2 bits per cell.
@@ -42,7 +39,6 @@ struct DevScen {
     const float4* rec;         // per-cell record
     const float* th8;          // slope (Eq. 1, degrees) toward each of the 8 neighbours
     float* q8;                 // f_p(p_propagate) of each of the 8 incoming edges (per run)
-    float* g8;                 // F e^z of each incoming edge (calibration) or nullptr
     const uint32_t* init;      // initial burning bit-plane (H * pitch words, packed at set-up)
     const uint32_t* fuel;      // fuel bit-plane
     uint32_t* planes[2];       // ping-pong state buffers

@@ -174,19 +174,17 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
     return x;
 }
 
-// d p_ignite / d(p_h, a, c1, c2) of cell j from tables: sm has bit m set for
-// each burning neighbour slot, q[m] its Eq. 5 value (0 for other slots, as
-// gathered from q8).  With dP/dq_m = prod over the other slots of (1 - q)
-// (prefix x suffix products), dq/dx = c (1 - q^2), dx/dp_h = F e^z (g8),
-// x = p_h F e^z and dx/d(a, c1, c2) = x (theta_s, V, V (cos - 1)).  No
-// transcendental function is evaluated; both adjoints call this routine, so
-// they agree cell by cell.
-// The table rows of cell j (rec, g8 and th8 entries) are passed in, so that a
+// d p_ignite / d(p_h, a, c1, c2) of cell j: sm has bit m set for each burning
+// neighbour slot, q[m] its Eq. 5 value (0 for other slots, as gathered from
+// q8).  With dP/dq_m = prod over the other slots of (1 - q) (prefix x suffix
+// products), dq/dx = c (1 - q^2), dx/dp_h = F e^z, x = p_h F e^z and
+// dx/d(a, c1, c2) = x (theta_s, V, V (cos - 1)).  One exponential per burning
+// slot; tanh is not re-evaluated (q comes from the table).  Both adjoints call
+// this routine, so they agree cell by cell.
+// The table rows of cell j (rec and th8 entries) are passed in, so that a
 // caller can issue their reads early.
-__device__ __forceinline__ void pignite_grad_tab(const DevScen& J, float4 rec, fs_f4 ga, fs_f4 gb,
-                                                 fs_f4 ta, fs_f4 tb, uint32_t sm,
-                                                 const float q[8], float gl[4]) {
-    const float gv[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+__device__ __forceinline__ void pignite_grad_tab(const DevScen& J, float4 rec, fs_f4 ta, fs_f4 tb,
+                                                 uint32_t sm, const float q[8], float gl[4]) {
     const float th[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
     float pre[8], suf[8], acc = 1.f;
 #pragma unroll
@@ -203,9 +201,12 @@ __device__ __forceinline__ void pignite_grad_tab(const DevScen& J, float4 rec, f
         float proj = (float)(-dc) * rec.z + (float)dr * rec.w;
         if (dr != 0 && dc != 0) proj = proj * kSqrtHalf;
         const float vterm = proj - rec.y;
-        const float x = J.p_h * gv[m];
+        // F e^z with the operations of edge_terms, so it has the bits the
+        // table pass used for q
+        const float gv = rec.x * expf(J.c1 * rec.y + J.c2 * vterm + J.a * th[m]);
+        const float x = J.p_h * gv;
         const float sc = pre[m] * suf[m] * (J.c * (1.f - q[m] * q[m]));
-        gl[0] = gl[0] + sc * gv[m];
+        gl[0] = gl[0] + sc * gv;
         gl[1] = gl[1] + sc * (x * th[m]);
         gl[2] = gl[2] + sc * (x * rec.y);
         gl[3] = gl[3] + sc * (x * vterm);
@@ -580,7 +581,6 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             constexpr int R = 1;
             const bool att = ADJ && attached(rings, t);
             const FS_GLOBAL fs_f4* q8v = (const FS_GLOBAL fs_f4*)q8g;
-            const FS_GLOBAL fs_f4* g8v = (const FS_GLOBAL fs_f4*)gmem(J.g8);
             const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
             // flat index of the region's top-left cell (may be negative; every
             // listed cell lies inside the grid)
@@ -588,7 +588,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             for (int k0 = 0; k0 < ntr; k0 += R * NT) {
                 int ent[R], ign[R];
                 fs_f4 qa[R], qb[R];
-                fs_f4 ga[R], gb[R], ta[R], tb[R];   // adjoint only
+                fs_f4 ta[R], tb[R];   // adjoint only
                 float4 rc[R];
                 float lj[R];
 #pragma unroll
@@ -600,7 +600,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     ent[r] &= 0x7FFF;
                     qa[r] = qb[r] = (fs_f4)(0.f);
                     if constexpr (ADJ) {
-                        ga[r] = gb[r] = ta[r] = tb[r] = (fs_f4)(0.f);
+                        ta[r] = tb[r] = (fs_f4)(0.f);
                         rc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
                         lj[r] = 0.f;
                     }
@@ -612,8 +612,6 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                         qb[r] = q8v[2 * j + 1];
                         if constexpr (ADJ) {
                             if (att && lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC) {
-                                ga[r] = g8v[2 * j];
-                                gb[r] = g8v[2 * j + 1];
                                 ta[r] = t8v[2 * j];
                                 tb[r] = t8v[2 * j + 1];
                                 rc[r] = load_f4(J.rec, j);
@@ -691,7 +689,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
 #pragma unroll
                                 for (int m = 0; m < 8; ++m) sm |= ((nm[m] >> bit) & 1u) << m;
                                 float gl[4];
-                                pignite_grad_tab(J, rc[r], ga[r], gb[r], ta[r], tb[r], sm, q, gl);
+                                pignite_grad_tab(J, rc[r], ta[r], tb[r], sm, q, gl);
 #pragma unroll
                                 for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj[r] * gl[m]);
                             }
@@ -843,28 +841,21 @@ k_slopes(DevScen J, float* __restrict__ th8, const float* __restrict__ slope9,
 __global__ void __launch_bounds__(256)
 k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, int32_t n,
          int64_t nvb) {
-    // one cell: q8 (and g8 in calibration handles) of its 8 incoming edges
+    // one cell: q8 of its 8 incoming edges
     auto cell = [&](const DevScen& J, int64_t j) {
         const float4 rec = load_f4(J.rec, j);
         const float4 ta = load_f4(J.th8, 2 * j), tb = load_f4(J.th8, 2 * j + 1);
         const float th[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
-        float q[8], g[8];
+        float q[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             int dr, dc;
             slot_dir(m, dr, dc);
-            const Edge e = edge_terms(J, rec, th[m], dr, dc);
-            q[m] = e.q;
-            g[m] = rec.x * e.ez;
+            q[m] = edge_terms(J, rec, th[m], dr, dc).q;
         }
         FS_GLOBAL fs_f4* o = (FS_GLOBAL fs_f4*)gmem(J.q8) + 2 * j;
         o[0] = fs_f4{q[0], q[1], q[2], q[3]};
         o[1] = fs_f4{q[4], q[5], q[6], q[7]};
-        if (J.g8) {
-            FS_GLOBAL fs_f4* og = (FS_GLOBAL fs_f4*)gmem(J.g8) + 2 * j;
-            og[0] = fs_f4{g[0], g[1], g[2], g[3]};
-            og[1] = fs_f4{g[4], g[5], g[6], g[7]};
-        }
     };
     // a fixed grid walks the 256-cell segments; the scenario of a segment's
     // first cell is found by advancing from the previous segment's
@@ -1161,11 +1152,9 @@ k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0
             float q[8];
 #pragma unroll
             for (int m = 0; m < 8; ++m) q[m] = ((sm >> m) & 1u) ? qv[m] : 0.f;
-            const FS_GLOBAL fs_f4* g8v = (const FS_GLOBAL fs_f4*)gmem(J.g8);
             const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
             float gl[4];
-            pignite_grad_tab(J, load_f4(J.rec, j), g8v[2 * j], g8v[2 * j + 1], t8v[2 * j],
-                             t8v[2 * j + 1], sm, q, gl);
+            pignite_grad_tab(J, load_f4(J.rec, j), t8v[2 * j], t8v[2 * j + 1], sm, q, gl);
             const float lj = lam[J.lam_off + j];
 #pragma unroll
             for (int m = 0; m < 4; ++m) g[m] = (double)(lj * gl[m]);
