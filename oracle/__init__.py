@@ -22,21 +22,40 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_lib = None
+# The same source built with OpenMP: fo_step and fo_pignite_map split their
+# row loops over threads (the per-cell arithmetic is unchanged).
+_LIB_OMP_PATH = os.path.join(_HERE, "liboracle_omp.so")
+_libs = {}
+_threads = 1
 
 # FP32 rounding of the f_p constant 1.1486328125 (Eq. 5 / 8).
 C_F32 = float(np.float32(1.1486328125))
 
 
 def build(force: bool = True) -> str:
-    """Compile ``fireoracle.c`` into ``liboracle.so`` (gcc, FP64, no fast-math)."""
+    """Compile ``fireoracle.c`` into ``liboracle.so`` (gcc, FP64, no fast-math)
+    and, from the same source with OpenMP, ``liboracle_omp.so``."""
     src = os.path.join(_HERE, "fireoracle.c")
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-o", tmp, src, "-lm"])
-        os.replace(tmp, _LIB_PATH)
+    for path, extra in ((_LIB_PATH, []), (_LIB_OMP_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared",
+                                   "-ffp-contract=off"] + extra + ["-o", tmp, src, "-lm"])
+            os.replace(tmp, path)
     return _LIB_PATH
+
+
+def set_threads(n: int) -> int:
+    """Use n host threads for the row loops of step / run / p_ignite maps
+    (n <= 1: the plain single-threaded build).  Returns the count in use."""
+    global _threads
+    _threads = max(1, int(n))
+    lib = _load()
+    return int(lib.fo_threads(_threads if _threads > 1 else 0))
+
+
+def threads() -> int:
+    return _threads
 
 
 class _Problem(ctypes.Structure):
@@ -57,12 +76,13 @@ class _Problem(ctypes.Structure):
 
 
 def _load():
-    global _lib
-    if _lib is not None:
-        return _lib
-    if not os.path.exists(_LIB_PATH):
+    key = "omp" if _threads > 1 else "plain"
+    if key in _libs:
+        return _libs[key]
+    path = _LIB_OMP_PATH if key == "omp" else _LIB_PATH
+    if not os.path.exists(path):
         build(force=False)
-    lib = ctypes.CDLL(_LIB_PATH)
+    lib = ctypes.CDLL(path)
     P = ctypes.POINTER(_Problem)
     vp = ctypes.c_void_p
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -81,11 +101,17 @@ def _load():
     lib.fo_next_cell.restype = ctypes.c_uint8
     lib.fo_run.argtypes = [P, i32, i32, vp, vp, vp, dbl]
     lib.fo_run.restype = i64
+    lib.fo_run_ties.argtypes = [P, i32, i32, vp, vp, vp, dbl, vp, vp, i64]
+    lib.fo_run_ties.restype = i64
+    lib.fo_threads.argtypes = [ctypes.c_int]
+    lib.fo_threads.restype = ctypes.c_int
     lib.fo_loss.argtypes = [i32, i32, vp, vp, i32, vp]
     lib.fo_loss.restype = dbl
     lib.fo_grad.argtypes = [P, i32, vp, vp, vp]
     lib.fo_slope_tensor.argtypes = [P, vp]
-    _lib = lib
+    if key == "omp":
+        lib.fo_threads(_threads)
+    _libs[key] = lib
     return lib
 
 
@@ -262,6 +288,24 @@ def run(scn, T, t0=0, S=None, tie_eps=1e-5, want_yhat=False, want_tstep=False, *
     ties = lib.fo_run(pb.ref, int(t0), int(T), S.ctypes.data, _ptr(yhat), _ptr(tstep),
                       float(tie_eps))
     return {"S": S, "ties": int(ties), "yhat": yhat, "tstep": tstep}
+
+
+def run_ties(scn, T, t0=0, S=None, tie_eps=1e-5, cap=1 << 20, want_yhat=False, **kw):
+    """Like ``run``, and lists the near ties: returns dict(S=..., ties=count,
+    tie_step=int32 array, tie_cell=int64 array (r*W + c), yhat=...), ties in
+    step and cell order."""
+    lib = _load()
+    pb = _problem(scn, **kw)
+    S = initial_state(scn) if S is None else np.array(S, dtype=np.uint8, copy=True)
+    S = np.ascontiguousarray(S)
+    yhat = (S == 1).astype(np.float64) if want_yhat else None
+    ts = np.zeros(cap, np.int32)
+    tc = np.zeros(cap, np.int64)
+    n = lib.fo_run_ties(pb.ref, int(t0), int(T), S.ctypes.data, _ptr(yhat), None,
+                        float(tie_eps), ts.ctypes.data, tc.ctypes.data, int(cap))
+    m = min(int(n), cap)
+    return {"S": S, "ties": int(n), "tie_step": ts[:m].copy(), "tie_cell": tc[:m].copy(),
+            "yhat": yhat}
 
 
 def loss(yhat, y, kind=0):

@@ -25,6 +25,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -188,6 +191,7 @@ double fo_pignite_cell(const fo_problem* pb, const uint8_t* S, int32_t r, int32_
 
 void fo_pignite_map(const fo_problem* pb, const uint8_t* S, double* out)
 {
+#pragma omp parallel for schedule(dynamic, 16)
     for (int32_t r = 0; r < pb->H; ++r)
         for (int32_t c = 0; c < pb->W; ++c)
             out[(int64_t)r * pb->W + c] = fo_pignite_cell(pb, S, r, c);
@@ -257,7 +261,12 @@ uint8_t fo_next_cell(const fo_problem* pb, int32_t t, const uint8_t* S_prev, int
         p = fo_pignite_cell(pb, S_prev, r, c);
         fo_draws(pb, t, j, &u_ign, NULL);
         next = (u_ign < (double)(float)p) ? 1 : 0;
-        tie = fabs(u_ign - p) <= tie_eps;
+        /* A near tie is a trial whose decision a different rounding of
+         * p_ignite could change.  Without fuel at j, or with p_h = 0, every
+         * edge has x = 0 exactly (Eq. 2), so p_ignite is exactly 0 in any
+         * precision and the trial can never succeed: not a tie. */
+        const double F = (1.0 + (double)pb->p_veg[j]) * (1.0 + (double)pb->p_den[j]);
+        tie = F > 0.0 && pb->p_h > 0.0 && fabs(u_ign - p) <= tie_eps;
     }
     if (p_out) *p_out = p;
     if (tie_out) *tie_out = tie;
@@ -268,6 +277,10 @@ int64_t fo_step(const fo_problem* pb, int32_t t, const uint8_t* S_prev, uint8_t*
                 double* yhat, uint8_t* tie, double tie_eps, double* pmap)
 {
     int64_t ties = 0;
+    /* Cells are independent within a step (every rule reads S(t-1) only), so
+     * the threaded build splits the rows; the per-cell arithmetic is the same
+     * in both builds. */
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : ties)
     for (int32_t r = 0; r < pb->H; ++r)
         for (int32_t c = 0; c < pb->W; ++c) {
             const int64_t j = (int64_t)r * pb->W + c;
@@ -285,18 +298,51 @@ int64_t fo_step(const fo_problem* pb, int32_t t, const uint8_t* S_prev, uint8_t*
 int64_t fo_run(const fo_problem* pb, int32_t t0, int32_t T, uint8_t* S, double* yhat,
                int32_t* tstep, double tie_eps)
 {
+    return fo_run_ties(pb, t0, T, S, yhat, tstep, tie_eps, NULL, NULL, 0);
+}
+
+int64_t fo_run_ties(const fo_problem* pb, int32_t t0, int32_t T, uint8_t* S, double* yhat,
+                    int32_t* tstep, double tie_eps, int32_t* tie_step, int64_t* tie_cell,
+                    int64_t cap)
+{
     const int64_t n = (int64_t)pb->H * pb->W;
     uint8_t* nxt = (uint8_t*)malloc((size_t)n);
+    uint8_t* tie = cap > 0 ? (uint8_t*)calloc((size_t)n, 1) : NULL;
     int64_t ties = 0;
     for (int32_t t = t0 + 1; t <= t0 + T; ++t) {
-        ties += fo_step(pb, t, S, nxt, yhat, NULL, tie_eps, NULL);
+        const int64_t k = fo_step(pb, t, S, nxt, yhat, tie, tie_eps, NULL);
+        if (tie && k > 0) {
+            /* list this step's near ties in cell order */
+            int64_t found = 0;
+            for (int64_t j = 0; j < n && found < k; ++j)
+                if (tie[j]) {
+                    if (ties + found < cap) {
+                        tie_step[ties + found] = t;
+                        tie_cell[ties + found] = j;
+                    }
+                    ++found;
+                }
+        }
+        ties += k;
         if (tstep)
             for (int64_t j = 0; j < n; ++j)
                 if (S[j] == 0 && nxt[j] == 1) tstep[j] = t;
         memcpy(S, nxt, (size_t)n);
     }
+    free(tie);
     free(nxt);
     return ties;
+}
+
+int fo_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* ----------------------------------------------------------------- Eq. 10 */

@@ -87,7 +87,9 @@ void fo_dpignite_cell(const fo_problem* pb, const uint8_t* S, int32_t r, int32_t
 
 /* The state at step t of cell (r, c) from S(t-1) = S_prev (the per-cell rule
  * of fo_step).  p_out (nullable) receives p_ignite for ignition trials, else 0;
- * tie_out (nullable) 1 for an ignition trial with |u - p| <= tie_eps. */
+ * tie_out (nullable) 1 for an ignition trial with |u - p| <= tie_eps whose
+ * receiving cell has fuel (with p_h > 0): trials at cells without fuel have
+ * p_ignite exactly 0 in any precision and are never near ties. */
 uint8_t fo_next_cell(const fo_problem* pb, int32_t t, const uint8_t* S_prev, int32_t r,
                      int32_t c, double* p_out, int* tie_out, double tie_eps);
 
@@ -104,6 +106,18 @@ int64_t fo_step(const fo_problem* pb, int32_t t, const uint8_t* S_prev, uint8_t*
  * the step at which each cell ignites.  Returns the near-tie count. */
 int64_t fo_run(const fo_problem* pb, int32_t t0, int32_t T, uint8_t* S, double* yhat,
                int32_t* tstep, double tie_eps);
+
+/* fo_run that also lists its near ties: the first `cap` of them in step and
+ * cell order go to tie_step[k] / tie_cell[k] (nullable when cap is 0).
+ * Returns the near-tie count (which may exceed cap). */
+int64_t fo_run_ties(const fo_problem* pb, int32_t t0, int32_t T, uint8_t* S, double* yhat,
+                    int32_t* tstep, double tie_eps, int32_t* tie_step, int64_t* tie_cell,
+                    int64_t cap);
+
+/* Threads of the row loops in fo_step / fo_pignite_map when the library is
+ * built with OpenMP (liboracle_omp.so): sets the count when n > 0 and returns
+ * the count in use (always 1 in the plain build). */
+int fo_threads(int n);
 
 /* Eq. 10: loss_kind 0 = BCE-with-logits on the bounding-box crop of
  * (yhat != 0) | (y != 0); 1 = BCE + MSE of 4x4 average pools; 2 = MSE only.

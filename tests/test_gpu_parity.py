@@ -672,11 +672,8 @@ def test_tie_log_covers_the_oracle_ties(Sim):
     assert np.array_equal(log["ignited"] == 1, log["draw"] < log["p_ignite"])
     assert np.all(log["scenario"] == 0)
     last = first[0] if first else T
-    # the oracle also flags draws near p = 0 at fuel-less cells, whose decision
-    # no rounding can change (the kernel never draws for them)
-    fuel = ((1.0 + s.p_veg.astype(np.float64)) * (1.0 + s.p_den.astype(np.float64)) > 0).ravel()
     for t in range(1, last + 1):
-        want = set(np.flatnonzero(ties[t].ravel() & fuel).tolist())
+        want = set(np.flatnonzero(ties[t].ravel()).tolist())
         got = set(log["cell"][log["step"] == t].tolist())
         assert want <= got, (t, sorted(want - got)[:5])
     if first:

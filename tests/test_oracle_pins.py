@@ -489,3 +489,65 @@ def test_next_cells_is_the_rule_of_step(oracle_lib):
     assert np.array_equal(nxt.reshape(S.shape), full)
     assert np.array_equal(t.reshape(S.shape), tie.astype(bool))
     np.testing.assert_array_equal(p.reshape(S.shape), pmap)
+
+
+# ------------------------------------------------------ near ties, threads
+
+def test_near_tie_needs_a_trial_that_rounding_can_change(oracle_lib):
+    """An ignition trial is a near tie when |u - p_ignite| <= eps; at a cell
+    without fuel (or with p_h = 0) every edge has x = 0 (Eq. 2), p_ignite is
+    exactly 0 in any precision and the trial is never a tie, whatever eps."""
+    eps = 0.5   # wide window, so that ordinary draws qualify
+    base = flat_scenario(3, 3)
+    S = np.zeros((3, 3), np.uint8)
+    S[0, 1] = 1                          # one burning neighbour of the centre
+    pb = oracle_lib.Problem(base)
+    t = next(t for t in range(1, 1000) if oracle_lib.draws(pb, t, 4)[0] <= 0.45)
+    u = oracle_lib.draws(pb, t, 4)[0]
+    # fuelled centre: p = tanh(c p_h) ~ 0.58 lies within eps of u
+    nxt, p, tie = oracle_lib.next_cells(base, t, S, [1], [1], tie_eps=eps)
+    assert p[0] == pytest.approx(math.tanh(C * float(np.float32(0.58))), rel=1e-12)
+    assert tie[0] == (abs(u - p[0]) <= eps) and tie[0]
+    # no fuel at the centre: p = 0, |u - p| <= eps, still not a tie
+    nofuel = dataclasses.replace(base, p_veg=base.p_veg.copy())
+    nofuel.p_veg[1, 1] = -1.0
+    nxt, p, tie = oracle_lib.next_cells(nofuel, t, S, [1], [1], tie_eps=eps)
+    assert p[0] == 0.0 and nxt[0] == 0 and not tie[0]
+    # p_h = 0: same
+    nxt, p, tie = oracle_lib.next_cells(base.with_params(p_h=0.0), t, S, [1], [1], tie_eps=eps)
+    assert p[0] == 0.0 and nxt[0] == 0 and not tie[0]
+
+
+def random_lakes_case(seed):
+    return synth.make_lakes(70, 83, seed, T=40, n_ignitions=3)
+
+
+def test_threaded_build_equals_plain_build(oracle_lib):
+    """The OpenMP build splits rows over threads; results must not change."""
+    s = random_lakes_case(5)
+    try:
+        oracle_lib.set_threads(1)
+        a = oracle_lib.run(s, 40, want_yhat=True, want_tstep=True)
+        pa = oracle_lib.pignite_map(s, a["S"])
+        oracle_lib.set_threads(4)
+        b = oracle_lib.run(s, 40, want_yhat=True, want_tstep=True)
+        pbm = oracle_lib.pignite_map(s, b["S"])
+    finally:
+        oracle_lib.set_threads(1)
+    assert np.array_equal(a["S"], b["S"]) and a["ties"] == b["ties"]
+    assert np.array_equal(a["yhat"], b["yhat"]) and np.array_equal(a["tstep"], b["tstep"])
+    assert np.array_equal(pa, pbm)
+
+
+def test_run_ties_lists_the_ties_of_each_step(oracle_lib):
+    s = random_lakes_case(6)
+    eps = 2e-3   # wide enough that a short run has ties to list
+    r = oracle_lib.run_ties(s, 40, tie_eps=eps)
+    S = oracle_lib.initial_state(s)
+    want = []
+    for t in range(1, 41):
+        S, tie, _, _ = oracle_lib.step(s, t, S, tie_eps=eps)
+        want += [(t, int(c)) for c in np.flatnonzero(tie.ravel())]
+    assert len(want) > 5 and r["ties"] == len(want)
+    assert list(zip(r["tie_step"].tolist(), r["tie_cell"].tolist())) == want
+    assert np.array_equal(r["S"], S)
