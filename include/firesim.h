@@ -163,6 +163,15 @@ SIM_API int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* w
 SIM_API int sim_set_exec(sim_handle* h, const sim_exec* e);
 SIM_API int sim_get_exec(const sim_handle* h, sim_exec* e);
 
+/* Build the per-edge propagation table (Eq. 2-5 for every edge the fire can
+ * reach in the next T steps) now.  sim_run builds it itself when needed
+ * (after sim_reset, sim_set_params, sim_set_wind, sim_set_state, sim_ignite,
+ * or when a run goes past the steps it was built for); calling sim_prepare
+ * first keeps that work out of a timed region or a captured launch sequence.
+ * The table covers the cells within (step + T - origin) cells of the burning
+ * cells at the origin step (the last reset, set_state or ignite). */
+SIM_API int sim_prepare(sim_handle* h, int32_t T);
+
 /* Autotuner: times every compiled execution shape (temporal depth = the
  * shape's halo, skipping on) over T_probe steps from the current state, keeps
  * the fastest and writes it to *best (nullable).  The state and step counter
@@ -187,7 +196,10 @@ SIM_API int sim_step(sim_handle* h);
 SIM_API int sim_get_step(const sim_handle* h, int32_t* step);
 
 /* Replace the parameters: `per_scenario` is a host array of n entries.
- * Takes effect from the next step. */
+ * Takes effect from the next step.  In calibration mode, a change after the
+ * run has started (step != 0) leaves the run's checkpoints and time maps
+ * under the old parameters: sim_adjoint and sim_loss_grad then return
+ * SIM_E_STATE until the next sim_reset. */
 SIM_API int sim_set_params(sim_handle* h, const sim_params* per_scenario);
 
 /* Restore every scenario to init_burning at step 0 and clear the
@@ -265,6 +277,15 @@ SIM_API int sim_counts(sim_handle* h, int64_t* out);
  * (device uint8 H*W, non-zero = affected): out (device int64 x 2) =
  * (|A intersect B|, |A union B|); Eq. 11's Jaccard index is their ratio. */
 SIM_API int sim_overlap(sim_handle* h, int32_t s, const uint8_t* target, int64_t* out);
+
+/* Eq. 11 and Eq. 12 against observed maps, all scenarios in one launch:
+ * `targets` is device uint8, the n grids concatenated (non-zero = observed
+ * affected cell); out (device int64, n x 4) receives per scenario
+ * (|A intersect B|, |A union B|, |A|, |B|), A = the scenario's affected cells
+ * (burning or burned) at the current step, B = its target's.  Jaccard (Eq. 11)
+ * is the first over the second; Eq. 12 sums |A| - |B| in absolute value over
+ * the observation times. */
+SIM_API int sim_metrics(sim_handle* h, const uint8_t* targets, int64_t* out);
 
 /* Probability of arrival from an ensemble of runs (Sec. 1): counts[j] (device
  * uint32 H*W, zeroed by the caller) += the number of scenarios s0 .. s0+n-1

@@ -357,3 +357,80 @@ def fd_grad(scn, T, y, kind=0, h_rel=1e-7, h_min=1e-9):
         g[k] = (Lp - Lm) / (2 * h)
         flips[k] = int(np.count_nonzero(outs[0]["tstep"] != outs[1]["tstep"]))
     return g, flips
+
+
+# ----------------------------------------------------------- Algorithm 1
+
+# Clamp ranges of Algorithm 1: p_h in [0.2, 1]; a, c1, c2 in [0, 1].
+CLAMP_LO = np.array([0.2, 0.0, 0.0, 0.0])
+CLAMP_HI = np.array([1.0, 1.0, 1.0, 1.0])
+
+
+class AdamW:
+    """AdamW (Adam with decoupled weight decay, Loshchilov & Hutter, ICLR 2019)
+    in FP64, with the defaults the paper's optimiser uses (Sec. 2.3: lr 5e-3;
+    betas (0.9, 0.999), eps 1e-8, weight decay 0.01):
+        theta <- theta (1 - lr wd)
+        m <- b1 m + (1 - b1) g,   v <- b2 v + (1 - b2) g^2
+        theta <- theta - lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps)."""
+
+    def __init__(self, theta, lr=5e-3, betas=(0.9, 0.999), eps=1e-8, weight_decay=0.01):
+        self.theta = np.array(theta, dtype=np.float64)
+        self.lr, self.b1, self.b2 = float(lr), float(betas[0]), float(betas[1])
+        self.eps, self.wd = float(eps), float(weight_decay)
+        self.m = np.zeros_like(self.theta)
+        self.v = np.zeros_like(self.theta)
+        self.t = 0
+
+    def step(self, g):
+        g = np.asarray(g, dtype=np.float64)
+        self.t += 1
+        self.theta = self.theta * (1.0 - self.lr * self.wd)
+        self.m = self.b1 * self.m + (1.0 - self.b1) * g
+        self.v = self.b2 * self.v + (1.0 - self.b2) * g * g
+        mhat = self.m / (1.0 - self.b1 ** self.t)
+        vhat = self.v / (1.0 - self.b2 ** self.t)
+        self.theta = self.theta - self.lr * mhat / (np.sqrt(vhat) + self.eps)
+        return self.theta
+
+
+def calibrate_sequence(scn, observations, theta0, interval, epochs=1, lr=5e-3, kind=0,
+                       winds=None, seed0=1000):
+    """Algorithm 1 with several observations per epoch, for one scenario: in
+    epoch ep the seed is seed0 + ep for every iteration; iteration it replays
+    the fire from its start for (it + 1) * interval steps under the current
+    parameters (rounded to FP32, the working precision) and, if given, the
+    wind winds[it] = (speed field or None, direction field or None, speed
+    scalar, direction scalar); takes the Eq. 10 loss against
+    observations[it] and its gradient, one AdamW step and the clamps.
+    Per iteration it also reports Eq. 11 (Jaccard of the affected areas at
+    the observation time) and Eq. 12 (the running sum over the epoch's
+    observation times of |affected count - observed count|).
+    Returns a list of dicts (epoch, iteration, loss, grad, theta, jaccard,
+    manhattan)."""
+    import dataclasses
+    opt = AdamW(theta0, lr=lr)
+    out = []
+    for ep in range(epochs):
+        manhattan = 0
+        for it, obs in enumerate(observations):
+            th = [float(np.float32(x)) for x in opt.theta]
+            sc = dataclasses.replace(scn, seed=seed0 + ep)
+            sc = sc.with_params(th[0], th[1], th[2], th[3])
+            if winds is not None:
+                ws, wd, ws0, wd0 = winds[it]
+                sc = dataclasses.replace(sc, wind_speed=ws, wind_dir=wd,
+                                         wind_speed_scalar=ws0, wind_dir_scalar=wd0)
+            T = (it + 1) * int(interval)
+            y = np.asarray(obs, dtype=np.uint8).reshape(scn.H, scn.W)
+            r = run(sc, T, want_yhat=True)
+            L, lam = loss(r["yhat"], y, kind)
+            g = grad(sc, T, lam)
+            A = affected(r["S"])
+            manhattan += abs(int(np.count_nonzero(A)) - int(np.count_nonzero(y)))
+            opt.step(g)
+            opt.theta = np.minimum(np.maximum(opt.theta, CLAMP_LO), CLAMP_HI)
+            out.append({"epoch": ep, "iteration": it, "loss": L, "grad": g,
+                        "theta": opt.theta.copy(), "jaccard": jaccard(A, y != 0),
+                        "manhattan": manhattan, "S": r["S"]})
+    return out

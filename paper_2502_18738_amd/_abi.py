@@ -75,6 +75,7 @@ EXPORTS = (
     "sim_pignite", "sim_accumulator", "sim_adjoint", "sim_loss_grad", "sim_stats",
     "sim_last_error", "sim_destroy", "sim_version", "sim_autotune", "sim_use_graphs",
     "sim_set_adjoint", "sim_set_wind", "sim_ignite", "sim_counts", "sim_overlap", "sim_arrival", "sim_tielog",
+    "sim_metrics", "sim_prepare",
 )
 
 _lib = None
@@ -124,6 +125,8 @@ def load():
         "sim_counts": (ctypes.c_int, [H, vp]),
         "sim_overlap": (ctypes.c_int, [H, i32, vp, vp]),
         "sim_arrival": (ctypes.c_int, [H, i32, i32, vp]),
+        "sim_metrics": (ctypes.c_int, [H, vp, vp]),
+        "sim_prepare": (ctypes.c_int, [H, i32]),
         "sim_tielog": (ctypes.c_int, [H, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():

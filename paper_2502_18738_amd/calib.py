@@ -104,7 +104,14 @@ def calibrate_sequence(sim: Sim, observations, theta0, *, interval: int, epochs:
     draws a new seed and keeps it for all of its iterations (Sec. 2.3); every
     iteration replays the fire from the start with the latest parameters,
     takes the Eq. 10 loss and its gradient, one AdamW step and the clamps.
-    Returns (theta, history of (epoch, iteration, loss per scenario, theta)).
+
+    Returns (theta, history): one dict per iteration with ``epoch``,
+    ``iteration``, ``loss`` (per scenario), ``grad`` (n x 4, the gradient the
+    step used), ``theta`` (after the step and the clamps), ``jaccard`` (Eq. 11
+    of the simulated and observed affected areas at the observation time,
+    per scenario) and ``manhattan`` (Eq. 12: the sum over this epoch's
+    observation times so far of the absolute difference of the affected-cell
+    counts, per scenario).  The counts come from the device (sim.metrics).
     """
     theta = torch.as_tensor(theta0, dtype=torch.float32, device=sim.device).clone()
     theta.requires_grad_(True)
@@ -112,6 +119,7 @@ def calibrate_sequence(sim: Sim, observations, theta0, *, interval: int, epochs:
     history = []
     for ep in range(epochs):
         seed = seed0 + ep
+        manhattan = torch.zeros(sim.n, dtype=torch.int64)
         for it, obs in enumerate(observations):
             p = theta.detach().to("cpu")
             sim.set_params([tuple(r) + (pc,) for r, pc in zip(p.tolist(), sim.p_continue)])
@@ -121,10 +129,16 @@ def calibrate_sequence(sim: Sim, observations, theta0, *, interval: int, epochs:
                     sim.set_wind(s_, *w)
             sim.run((it + 1) * int(interval))
             y = torch.as_tensor(obs, device=sim.device).to(torch.uint8).view(-1)
+            m = sim.metrics(y).cpu()          # |A & B|, |A | B|, |A|, |B| per scenario
             loss, grad = sim.loss_grad(y, loss_kind)
             theta.grad = grad.to(theta.dtype)
             opt.step()
             opt.zero_grad(set_to_none=True)
             clamp_(theta)
-            history.append((ep, it, loss.detach().cpu(), theta.detach().cpu().clone()))
+            manhattan = manhattan + (m[:, 2] - m[:, 3]).abs()
+            jac = torch.where(m[:, 1] > 0, m[:, 0].double() / m[:, 1].clamp(min=1).double(),
+                              torch.ones(sim.n, dtype=torch.float64))
+            history.append({"epoch": ep, "iteration": it, "loss": loss.detach().cpu(),
+                            "grad": grad.detach().cpu(), "theta": theta.detach().cpu().clone(),
+                            "jaccard": jac, "manhattan": manhattan.clone()})
     return theta.detach(), history

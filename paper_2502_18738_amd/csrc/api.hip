@@ -37,7 +37,7 @@ struct ScenLayout {
 
 struct Layout {
     size_t err, stats, box, part, jobs, tile_job, adj_jobs, adj_tile_job, gpart, ranges, lam,
-        cell0, bl0, ib0, gpart_tmap, masks, adj_masks, tielog, tie_n, total;
+        cell0, bl0, ib0, gpart_tmap, masks, adj_masks, tielog, tie_n, fbox, qbox, cell0q, total;
     int32_t mask_words, adj_mask_words;
     int64_t total_cells;
     int32_t tmap_blocks;
@@ -73,6 +73,9 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
     L->jobs = take(sizeof(fs::DevScen) * (size_t)n);
     L->cell0 = take(sizeof(int64_t) * (size_t)(n + 1));
     L->ib0 = take(sizeof(int32_t) * (size_t)(n + 1));
+    L->fbox = take(16 * (size_t)n);                     // burning box at the table's origin step
+    L->qbox = take(16 * (size_t)n);                     // table region per scenario
+    L->cell0q = take(sizeof(int64_t) * (size_t)(n + 1));
     L->total_cells = 0;
     for (int i = 0; i < n; ++i) L->total_cells += (int64_t)d[i].H * d[i].W;
     int64_t tiles = 0;
@@ -230,6 +233,13 @@ struct sim_handle {
     std::vector<Graph> graphs;
     bool use_graphs = true;
     bool q_dirty = true;            // q8 tables must be rebuilt before the next step
+    // The table covers the cells within (q_end - q_origin) of the burning box
+    // taken at step q_origin: every ignition trial up to step q_end.
+    int q_origin = 0, q_end = 0;
+    // calibration mode: the parameters changed after the run started, so the
+    // checkpoints / time maps no longer match the parameters an adjoint would
+    // differentiate; cleared by sim_reset
+    bool stale = false;
     int adj_method = 0;             // 0: checkpoint recompute, 1: time maps
     fs::Rings rings{-1, 0, 0, 0};   // step-ring attach set (first < 0: every step)
     std::vector<int32_t> bl0;
@@ -251,6 +261,7 @@ struct sim_handle {
     int* d_err() { return reinterpret_cast<int*>(ws + L.err); }
     unsigned long long* d_stats() { return reinterpret_cast<unsigned long long*>(ws + L.stats); }
     unsigned long long* d_masks() { return reinterpret_cast<unsigned long long*>(ws + L.masks); }
+    int4* d_fbox() { return reinterpret_cast<int4*>(ws + L.fbox); }
     bool calib() const { return flags & SIM_F_CALIB; }
 
     int fail(int code, const char* fmt, ...) {
@@ -323,6 +334,15 @@ int refresh_worklist(sim_handle* h, bool dup) {
     return rc;
 }
 
+// The state changed other than by stepping (reset, set_state, spotting):
+// the propagation table is rebuilt around the new burning box.
+int take_origin(sim_handle* h, int origin_step) {
+    h->q_dirty = true;
+    h->q_origin = origin_step;
+    return h->hip(fs::launch_bbox(h->st, h->d_jobs(), h->n, h->parity, h->max_words, h->d_fbox()),
+                  "burning box");
+}
+
 int save_ckpt(sim_handle* h, int slot) {
     return h->hip(fs::launch_ckpt_save(h->st, h->d_jobs(), h->n, h->parity, slot, h->max_words),
                   "checkpoint");
@@ -331,7 +351,7 @@ int save_ckpt(sim_handle* h, int slot) {
 int reset_state(sim_handle* h) {
     h->parity = 0;
     h->step = 0;
-    h->q_dirty = true;   // every run from a reset rebuilds the propagation table
+    // every run from a reset rebuilds the propagation table (take_origin)
     int rc = h->hip(fs::launch_init_state(h->st, h->d_jobs(),
                                           reinterpret_cast<const int32_t*>(h->ws + h->L.ib0),
                                           h->n, h->ib0.back(),
@@ -339,6 +359,7 @@ int reset_state(sim_handle* h) {
                                           h->L.total_cells, h->calib()), "init state");
     if (rc) return rc;
     rc = refresh_worklist(h, false);   // init_state wrote both buffers
+    if (!rc) rc = take_origin(h, 0);
     if (rc) return rc;
     rc = h->hip(hipMemsetAsync(h->d_stats(), 0, 4 * sizeof(unsigned long long), h->st),
                 "clear stats");
@@ -480,6 +501,13 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
     for (int i = 0; i < n && !rc; ++i)
         rc = h->hip(fs::launch_slopes(h->st, h->job[i], const_cast<float*>(h->job[i].th8),
                                       descs[i].f.slope_deg, h->d_err()), "slope table");
+    // Table entries outside the region a run can reach are never read; they
+    // start as NaN, so that a read outside the region (a defect) could only
+    // make p_ignite NaN and the trial fail visibly, never pass silently.
+    for (int i = 0; i < n && !rc; ++i)
+        rc = h->hip(fs::launch_fill_u32(h->st, reinterpret_cast<uint32_t*>(h->job[i].q8),
+                                        (size_t)8 * descs[i].H * descs[i].W, 0x7FC00000u),
+                    "table fill");
     // keep the packed initial burning plane for every reset
     for (int i = 0; i < n && !rc; ++i)
         rc = h->hip(hipMemcpyAsync(const_cast<uint32_t*>(h->job[i].init), h->job[i].planes[0],
@@ -590,14 +618,24 @@ int enqueue_run(sim_handle* h, hipStream_t st, int T, unsigned long long* stats)
     return SIM_OK;
 }
 
-// Rebuild the per-edge propagation table (Eq. 2-5 for every edge) if the
-// parameters changed or a new run started since it was built.
-int ensure_qtable(sim_handle* h) {
-    if (!h->q_dirty) return SIM_OK;
-    int rc = h->hip(fs::launch_qtable(h->st, h->d_jobs(),
-                                      reinterpret_cast<const int64_t*>(h->ws + h->L.cell0), h->n,
-                                      h->L.total_cells), "propagation table");
-    if (!rc) h->q_dirty = false;
+// Make the per-edge propagation table (Eq. 2-5 for every edge) valid for
+// every ignition trial up to step t_end: rebuilt when the parameters, the
+// wind or the state's origin changed, or when t_end passes the steps it was
+// built for.  It covers the cells within t_end - q_origin of the burning box
+// at step q_origin: fire moves at most one cell per step, so a cell with a
+// burning neighbour at step t - 1 <= t_end - 1 lies within t - q_origin of it.
+int ensure_qtable(sim_handle* h, int64_t t_end) {
+    if (!h->q_dirty && t_end <= h->q_end) return SIM_OK;
+    const int reach = (int)std::min<int64_t>(std::max<int64_t>(t_end - h->q_origin, 0), kMaxSide);
+    int rc = h->hip(fs::launch_qtable(h->st, h->d_jobs(), h->d_fbox(), h->n, reach,
+                                      h->L.total_cells,
+                                      reinterpret_cast<int4*>(h->ws + h->L.qbox),
+                                      reinterpret_cast<int64_t*>(h->ws + h->L.cell0q)),
+                    "propagation table");
+    if (!rc) {
+        h->q_dirty = false;
+        h->q_end = (int)std::min<int64_t>(t_end, INT_MAX);
+    }
     return rc;
 }
 
@@ -675,7 +713,7 @@ int sim_run(sim_handle* h, int32_t T) {
         return h->fail(SIM_E_STATE, "calibration run would pass T_max = %d", h->T_max);
     if ((int64_t)h->step + T > INT_MAX / 2) return h->fail(SIM_E_SHAPE, "step counter overflow");
     if (T == 0) return SIM_OK;
-    int qrc = ensure_qtable(h);
+    int qrc = ensure_qtable(h, (int64_t)h->step + T);
     if (qrc) return qrc;
     unsigned long long* stats = (h->flags & SIM_F_STATS) ? h->d_stats() : nullptr;
     if (h->use_graphs && !stats && T > h->ex.depth) {
@@ -685,13 +723,19 @@ int sim_run(sim_handle* h, int32_t T) {
     return enqueue_run(h, h->st, T, stats);
 }
 
+int sim_prepare(sim_handle* h, int32_t T) {
+    if (!h) return SIM_E_ARG;
+    if (T < 0) return h->fail(SIM_E_SHAPE, "T must be >= 0");
+    return ensure_qtable(h, (int64_t)h->step + T);
+}
+
 int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best) {
     if (!h) return SIM_E_ARG;
     if (h->calib()) return h->fail(SIM_E_STATE, "sim_autotune is not available in calibration mode");
     if (T_probe < 1 || T_probe > 4096) return h->fail(SIM_E_SHAPE, "T_probe must be in [1, 4096]");
     fs::TileShape shapes[64];
     const int ns = fs::step_shapes(shapes, 64);
-    if (int r = ensure_qtable(h)) return r;
+    if (int r = ensure_qtable(h, (int64_t)h->step + T_probe)) return r;
     const int step0 = h->step, par0 = h->parity;
     const sim_exec ex0 = h->ex;
     int rc = SIM_OK;
@@ -795,6 +839,7 @@ int sim_set_params(sim_handle* h, const sim_params* p) {
     }
     h->adj_T = -1;  // adjoint jobs copy the parameters
     h->q_dirty = true;
+    if (h->calib() && h->step != 0) h->stale = true;
     return SIM_OK;
 }
 
@@ -817,6 +862,7 @@ int sim_reset(sim_handle* h, const uint64_t* seeds) {
         }
         h->adj_T = -1;
     }
+    h->stale = false;
     return reset_state(h);
 }
 
@@ -839,6 +885,7 @@ int sim_set_state(sim_handle* h, int32_t s, const uint8_t* in, int32_t step) {
     if (!rc) rc = h->hip(fs::launch_set_state(h->st, J, in, J.planes[h->parity], h->d_err()),
                          "set state");
     if (!rc) rc = refresh_worklist(h, true);
+    if (!rc) rc = take_origin(h, step);
     int bad = 0;
     if (!rc) rc = h->hip(hipMemcpyAsync(&bad, h->d_err(), sizeof(int), hipMemcpyDeviceToHost,
                                         h->st), "read error flag");
@@ -920,14 +967,17 @@ int build_adjoint(sim_handle* h, int T) {
 }
 
 int adjoint(sim_handle* h, const float* lam, double* grad) {
+    if (h->stale)
+        return h->fail(SIM_E_STATE, "the parameters changed after the run started; "
+                       "sim_reset and sim_run again before the adjoint");
     const int T = h->step;
     if (T == 0)
         return h->hip(hipMemsetAsync(grad, 0, sizeof(double) * 4 * (size_t)h->n, h->st),
                       "zero gradient");
     fs::Rings rg = h->rings;
     rg.T = T;
-    // both adjoints read the q8 table of the current parameters
-    if (int rc = ensure_qtable(h)) return rc;
+    // both adjoints read the q8 table of the run's parameters
+    if (int rc = ensure_qtable(h, T)) return rc;
     if (h->adj_method == 1) {
         auto* gp = reinterpret_cast<double*>(h->ws + h->L.gpart_tmap);
         int rc = h->hip(fs::launch_adjoint_tmap(h->st, h->d_jobs(),
@@ -1007,6 +1057,9 @@ int sim_loss_grad(sim_handle* h, const uint8_t* target, int32_t kind, double* lo
     if (!target || !loss || !grad) return h->fail(SIM_E_ARG, "target, loss, grad must be non-NULL");
     if (kind < SIM_LOSS_BCE || kind > SIM_LOSS_MSE) return h->fail(SIM_E_ARG, "bad loss kind");
     if (!h->calib()) return h->fail(SIM_E_STATE, "sim_loss_grad needs SIM_F_CALIB");
+    if (h->stale)
+        return h->fail(SIM_E_STATE, "the parameters changed after the run started; "
+                       "sim_reset and sim_run again before the loss and its gradient");
     float* lam = reinterpret_cast<float*>(h->ws + h->L.lam);
     int rc = h->hip(fs::launch_loss(h->st, h->d_jobs(),
                                     reinterpret_cast<const int64_t*>(h->ws + h->L.cell0), h->n,
@@ -1059,6 +1112,7 @@ int sim_ignite(sim_handle* h, int32_t s, const int32_t* cells, int32_t count) {
     if (count == 0) return SIM_OK;
     int rc = h->hip(fs::launch_ignite(h->st, h->job[s], cells, count), "ignite");
     if (!rc) rc = refresh_worklist(h, false);   // both buffers were written
+    if (!rc) rc = take_origin(h, h->step);
     return rc;
 }
 
@@ -1075,6 +1129,18 @@ int sim_overlap(sim_handle* h, int32_t s, const uint8_t* target, int64_t* out) {
     if (!target || !out) return h->fail(SIM_E_ARG, "target and out must be non-NULL");
     return h->hip(fs::launch_overlap(h->st, h->job[s], h->parity, target,
                                      reinterpret_cast<long long*>(out)), "overlap");
+}
+
+int sim_metrics(sim_handle* h, const uint8_t* targets, int64_t* out) {
+    if (!h) return SIM_E_ARG;
+    if (!targets || !out) return h->fail(SIM_E_ARG, "targets and out must be non-NULL");
+    if ((uintptr_t)out & 7u) return h->fail(SIM_E_ARG, "out must be 8-byte aligned");
+    int64_t max_cells = 0;
+    for (const auto& J : h->job) max_cells = std::max<int64_t>(max_cells, (int64_t)J.H * J.W);
+    return h->hip(fs::launch_metrics(h->st, h->d_jobs(),
+                                     reinterpret_cast<const int64_t*>(h->ws + h->L.cell0), h->n,
+                                     h->parity, max_cells, targets,
+                                     reinterpret_cast<long long*>(out)), "metrics");
 }
 
 int sim_arrival(sim_handle* h, int32_t s0, int32_t n, uint32_t* counts) {

@@ -105,16 +105,27 @@ hipError_t launch_ignite(hipStream_t st, const DevScen& job, const int32_t* cell
 // out[2s], out[2s+1] += burning / burned counts of every job (out zeroed first).
 hipError_t launch_counts(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
                          int64_t max_words, long long* out);
-// out = (|A & B|, |A | B|) for affected cells A of one job and target B.
+// out[4 s ..] = (|A & B|, |A | B|, |A|, |B|) of every job s: A its affected
+// cells, B the non-zero cells of its target grid (concatenated at d_cell0[s]).
+hipError_t launch_metrics(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
+                          int32_t parity, int64_t max_cells, const uint8_t* target,
+                          long long* out);
 // counts[j] += scenarios s0 .. s0+n-1 (shape of J0 = job s0) in which j is affected
 hipError_t launch_arrival(hipStream_t st, const DevScen* d_jobs, const DevScen& J0, int32_t s0,
                           int32_t n, int32_t parity, uint32_t* counts);
+// out = (|A & B|, |A | B|) for affected cells A of one job and target B.
 hipError_t launch_overlap(hipStream_t st, const DevScen& job, int32_t parity, const uint8_t* target,
                           long long* out);
-// Propagation table q8 of every scenario for the current parameters.
-// d_cell0: n + 1 prefix sums of cell counts (block ranges per scenario).
-hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
-                         int64_t total_cells);
+// box[s] = (r0, r1, c0, c1), the bounding box of the burning cells of every
+// scenario in planes[parity] (r1 < r0: nothing burns).
+hipError_t launch_bbox(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
+                       int64_t max_words, int4* box);
+// Propagation table q8 of every scenario for the current parameters, over the
+// cells within `reach` of box[s] (the only cells that can have an ignition
+// trial in the next `reach` steps); qbox (n) and cell0q (n + 1) are scratch
+// for the regions and their prefix sums; max_cells bounds their total.
+hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int4* box, int32_t n,
+                         int32_t reach, int64_t max_cells, int4* qbox, int64_t* cell0q);
 // State of every scenario back to its initial burning cells (both ping-pong
 // buffers; with maps, also the accumulator and time maps); d_ib0 = n + 1
 // prefix sums of the blocks per scenario, ceil(H * pitch / 256).

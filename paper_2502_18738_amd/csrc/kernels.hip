@@ -835,12 +835,97 @@ k_slopes(DevScen J, float* __restrict__ th8, const float* __restrict__ slope9,
     o[1] = make_float4(th[4], th[5], th[6], th[7]);
 }
 
-// q8[j][m] = f_p(p_propagate) of the edge from slot m into cell j (Eq. 2-5)
-// for every cell of every scenario; one flat grid, blocks mapped to scenarios
-// through the prefix sums of their cell counts.
+// Bounding box (r0, r1, c0, c1) of the burning cells of every scenario in
+// planes[parity] (r1 < r0 when nothing burns): the fire can only reach cells
+// within t steps of it t steps later (one Moore neighbour per step).
+__global__ void k_bbox_clear(int4* __restrict__ box, int32_t n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) box[i] = make_int4(INT_MAX, -1, INT_MAX, -1);
+}
+
 __global__ void __launch_bounds__(256)
-k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, int32_t n,
-         int64_t nvb) {
+k_bbox(const DevScen* __restrict__ jobs, int32_t parity, int4* __restrict__ box) {
+    const DevScen& J = jobs[blockIdx.y];
+    const int64_t PW = (int64_t)J.H * J.pitch;
+    const FS_GLOBAL uint32_t* B = gmem(J.planes[parity]);
+    int r0 = INT_MAX, r1 = -1, c0 = INT_MAX, c1 = -1;
+    for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < PW;
+         o += (int64_t)gridDim.x * 256) {
+        const uint32_t w = B[o];
+        if (w) {
+            const int r = (int)(o / J.pitch), cw = (int)(o - (int64_t)r * J.pitch);
+            r0 = min(r0, r);
+            r1 = max(r1, r);
+            c0 = min(c0, 32 * cw + __builtin_ctz(w));
+            c1 = max(c1, 32 * cw + 31 - __builtin_clz(w));
+        }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        r0 = min(r0, __shfl_down(r0, d, 64));
+        r1 = max(r1, __shfl_down(r1, d, 64));
+        c0 = min(c0, __shfl_down(c0, d, 64));
+        c1 = max(c1, __shfl_down(c1, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0 && r1 >= 0) {
+        int* b = reinterpret_cast<int*>(box + blockIdx.y);
+        atomicMin(&b[0], r0);
+        atomicMax(&b[1], r1);
+        atomicMin(&b[2], c0);
+        atomicMax(&b[3], c1);
+    }
+}
+
+// Region of the propagation table for the next steps: the burning box of
+// each scenario grown by `reach` cells and clipped to the grid, as (r0, c0,
+// width, height) with the prefix sums of the region sizes in cell0q[0..n]
+// (one work-group; a thread takes a contiguous run of scenarios).
+__global__ void __launch_bounds__(256)
+k_qbox(const DevScen* __restrict__ jobs, const int4* __restrict__ box, int32_t n, int32_t reach,
+       int4* __restrict__ qbox, int64_t* __restrict__ cell0q) {
+    __shared__ long long sPart[256];
+    const int per = (n + 255) / 256;
+    const int a = min(n, (int)threadIdx.x * per), b = min(n, a + per);
+    long long sum = 0;
+    for (int i = a; i < b; ++i) {
+        const int4 bb = box[i];
+        const DevScen& J = jobs[i];
+        int4 q = make_int4(0, 0, 0, 0);
+        if (bb.y >= bb.x) {
+            const int r0 = max(0, bb.x - reach), r1 = min(J.H - 1, bb.y + reach);
+            const int c0 = max(0, bb.z - reach), c1 = min(J.W - 1, bb.w + reach);
+            q = make_int4(r0, c0, c1 - c0 + 1, r1 - r0 + 1);
+        }
+        qbox[i] = q;
+        sum += (long long)q.z * q.w;
+    }
+    sPart[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long acc = 0;
+        for (int k = 0; k < 256; ++k) {
+            const long long v = sPart[k];
+            sPart[k] = acc;
+            acc += v;
+        }
+        cell0q[n] = acc;
+    }
+    __syncthreads();
+    long long off = sPart[threadIdx.x];
+    for (int i = a; i < b; ++i) {
+        cell0q[i] = off;
+        const int4 q = qbox[i];
+        off += (long long)q.z * q.w;
+    }
+}
+
+// q8[j][m] = f_p(p_propagate) of the edge from slot m into cell j (Eq. 2-5)
+// for every cell of each scenario's table region; one flat index over the
+// regions of all scenarios, mapped to scenarios through the prefix sums of
+// the region sizes.  A fixed grid walks the 256-cell segments.
+__global__ void __launch_bounds__(256)
+k_qtable(const DevScen* __restrict__ jobs, const int4* __restrict__ qbox,
+         const int64_t* __restrict__ cell0, int32_t n) {
     // one cell: q8 of its 8 incoming edges
     auto cell = [&](const DevScen& J, int64_t j) {
         const float4 rec = load_f4(J.rec, j);
@@ -857,8 +942,14 @@ k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, in
         o[0] = fs_f4{q[0], q[1], q[2], q[3]};
         o[1] = fs_f4{q[4], q[5], q[6], q[7]};
     };
-    // a fixed grid walks the 256-cell segments; the scenario of a segment's
-    // first cell is found by advancing from the previous segment's
+    // region index i of scenario s -> grid cell
+    auto at = [&](int s, int64_t i) {
+        const int4 q = qbox[s];
+        const int rr = (int)(i / q.z);
+        return (int64_t)(q.x + rr) * jobs[s].W + (q.y + (int)(i - (int64_t)rr * q.z));
+    };
+    const int64_t total = cell0[n];
+    const int64_t nvb = (total + 255) / 256;
     int lo = 0;   // scenario s with cell0[s] <= g0 < cell0[s + 1]; g0 only grows
     {
         const int64_t g0 = (int64_t)blockIdx.x * 256;
@@ -868,7 +959,6 @@ k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, in
             if (cell0[mid] <= g0) lo = mid; else hi = mid;
         }
     }
-    const int64_t total = cell0[n];
     for (int64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
         const int64_t g0 = vb * 256;
         while (lo < n - 1 && g0 >= cell0[lo + 1]) ++lo;
@@ -876,11 +966,11 @@ k_qtable(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, in
         if (g0 + 256 <= cell0[lo + 1]) {
             // the whole segment lies in scenario lo: its descriptor is uniform
             const int su = __builtin_amdgcn_readfirstlane(lo);
-            cell(jobs[su], gi - cell0[su]);
+            cell(jobs[su], at(su, gi - cell0[su]));
         } else if (gi < total) {
             int s = lo;   // the segment straddles scenarios
             while (gi >= cell0[s + 1]) ++s;
-            cell(jobs[s], gi - cell0[s]);
+            cell(jobs[s], at(s, gi - cell0[s]));
         }
     }
 }
@@ -970,6 +1060,45 @@ k_overlap(DevScen J, int32_t parity, const uint8_t* __restrict__ target,
     if ((threadIdx.x & 63) == 0) {
         if (in) atomicAdd((unsigned long long*)&out[0], (unsigned long long)in);
         if (un) atomicAdd((unsigned long long*)&out[1], (unsigned long long)un);
+    }
+}
+
+// Eq. 11 and Eq. 12 inputs of every scenario against its observed map, one
+// launch: out[4 s .. 4 s + 3] += (|A & B|, |A | B|, |A|, |B|) with A the
+// affected cells (burning or burned) of scenario s = blockIdx.y and B the
+// non-zero cells of its target (concatenated grids, scenario s at cell0[s]).
+__global__ void __launch_bounds__(256)
+k_metrics(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0,
+          int32_t parity, const uint8_t* __restrict__ target, long long* __restrict__ out) {
+    const DevScen& J = jobs[blockIdx.y];
+    const int64_t HW = (int64_t)J.H * J.W, PW = (int64_t)J.H * J.pitch;
+    const uint32_t* B = J.planes[parity];
+    const uint8_t* y = target + cell0[blockIdx.y];
+    long long in = 0, un = 0, na = 0, nb = 0;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < HW;
+         j += (int64_t)gridDim.x * 256) {
+        const int r = (int)(j / J.W), c = (int)(j - (int64_t)r * J.W);
+        const int64_t o = (int64_t)r * J.pitch + (c >> 5);
+        const bool a = ((B[o] | B[PW + o]) >> (c & 31)) & 1u;
+        const bool b = y[j] != 0;
+        in += a && b;
+        un += a || b;
+        na += a;
+        nb += b;
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        in += __shfl_down(in, d, 64);
+        un += __shfl_down(un, d, 64);
+        na += __shfl_down(na, d, 64);
+        nb += __shfl_down(nb, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        unsigned long long* o = (unsigned long long*)out + 4 * blockIdx.y;
+        if (in) atomicAdd(&o[0], (unsigned long long)in);
+        if (un) atomicAdd(&o[1], (unsigned long long)un);
+        if (na) atomicAdd(&o[2], (unsigned long long)na);
+        if (nb) atomicAdd(&o[3], (unsigned long long)nb);
     }
 }
 
@@ -1592,6 +1721,16 @@ hipError_t launch_counts(hipStream_t st, const DevScen* d_jobs, int32_t n, int32
     return hipGetLastError();
 }
 
+hipError_t launch_metrics(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
+                          int32_t parity, int64_t max_cells, const uint8_t* target,
+                          long long* out) {
+    hipError_t e = launch_fill_u32(st, reinterpret_cast<uint32_t*>(out), (size_t)n * 8, 0u);
+    if (e != hipSuccess || n <= 0) return e;
+    const unsigned gx = (unsigned)std::min<int64_t>((max_cells + 255) / 256, 512);
+    hipLaunchKernelGGL(k_metrics, dim3(gx, n), dim3(256), 0, st, d_jobs, d_cell0, parity, target,
+                       out);
+    return hipGetLastError();
+}
 hipError_t launch_overlap(hipStream_t st, const DevScen& J, int32_t parity, const uint8_t* target,
                           long long* out) {
     hipError_t e = launch_fill_u32(st, reinterpret_cast<uint32_t*>(out), 4, 0u);
@@ -1607,12 +1746,24 @@ hipError_t launch_arrival(hipStream_t st, const DevScen* d_jobs, const DevScen& 
     return hipGetLastError();
 }
 
-hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
-                         int64_t total_cells) {
-    if (total_cells <= 0) return hipSuccess;
-    const int64_t nvb = (total_cells + 255) / 256;
-    hipLaunchKernelGGL(k_qtable, dim3((unsigned)std::min<int64_t>(nvb, 16384)), dim3(256), 0, st,
-                       d_jobs, d_cell0, n, nvb);
+hipError_t launch_bbox(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
+                       int64_t max_words, int4* box) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bbox_clear, dim3((n + 255) / 256), dim3(256), 0, st, box, n);
+    const unsigned gx = (unsigned)std::min<int64_t>((max_words + 255) / 256, 256);
+    hipLaunchKernelGGL(k_bbox, dim3(gx, n), dim3(256), 0, st, d_jobs, parity, box);
+    return hipGetLastError();
+}
+
+hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int4* box, int32_t n,
+                         int32_t reach, int64_t max_cells, int4* qbox, int64_t* cell0q) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_qbox, dim3(1), dim3(256), 0, st, d_jobs, box, n, reach, qbox, cell0q);
+    // the region sizes are known on the device only: a grid that covers the
+    // largest possible total walks what is there
+    const int64_t nvb = (max_cells + 255) / 256;
+    hipLaunchKernelGGL(k_qtable, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(nvb, 8192))),
+                       dim3(256), 0, st, d_jobs, qbox, cell0q, n);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@ runs in the library's HIP kernels.
 
 from __future__ import annotations
 
+import contextlib
 import ctypes
 from typing import Iterable, Optional, Sequence
 
@@ -56,6 +57,14 @@ class Sim:
             T_max = max(int(getattr(s, "T", 0)) for s in scenarios)
         T_max = int(T_max or 0)
         self._keep = []
+        self._h = None
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with self._on_stream():
+            self._init(scenarios, flags, int(ckpt_every), T_max)
+        if exec is not None:
+            self.set_exec(**exec)
+
+    def _init(self, scenarios, flags, ckpt_every, T_max):
         descs = (_abi.sim_desc * self.n)()
         for i, s in enumerate(scenarios):
             f32 = lambda a: _dev_tensor(a, torch.float32, self.device)
@@ -82,7 +91,6 @@ class Sim:
                                      int(s.scenario_id) & 0xFFFFFFFF,
                                      int(s.seed) & 0xFFFFFFFFFFFFFFFF, par, fields)
         self._descs = descs
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         nbytes = self._lib.sim_workspace_size(descs, self.n, flags, int(ckpt_every), T_max)
         if nbytes == 0:
             raise SimError(_abi.SIM_E_ARG, "invalid scenario descriptions")
@@ -96,16 +104,41 @@ class Sim:
         if rc != 0:
             raise SimError(rc, self._lib.sim_last_error(None).decode())
         self._h = h
-        if exec is not None:
-            self.set_exec(**exec)
 
     # ------------------------------------------------------------ plumbing
     def _check(self, rc):
         if rc != 0:
             raise SimError(rc, self._lib.sim_last_error(self._h).decode())
 
+    @contextlib.contextmanager
+    def _on_stream(self, inputs=(), outputs=()):
+        """Run a library call on the handle's stream.  When the caller works on
+        another stream: the handle's stream first waits for the caller's work
+        (inputs it produced are complete), temporaries are allocated on the
+        handle's stream, the caller's input tensors are marked as used there
+        (the allocator does not hand their memory out while the library may
+        still read them), and afterwards the caller's stream waits for the
+        library's work and the outputs are marked as used on it."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur == self.stream:
+            yield
+            return
+        self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            yield
+        for t in inputs:
+            if isinstance(t, torch.Tensor) and t.is_cuda:
+                t.record_stream(self.stream)
+        cur.wait_stream(self.stream)
+        for t in outputs:
+            if isinstance(t, torch.Tensor) and t.is_cuda:
+                t.record_stream(cur)
+
     def close(self):
         if getattr(self, "_h", None):
+            # the workspace and fields are freed with this object: let the
+            # handle's queued work finish first
+            self.stream.synchronize()
             self._lib.sim_destroy(self._h)
             self._h = None
 
@@ -120,7 +153,8 @@ class Sim:
         """skip: 0 process every tile, 1 (or True) device worklist, 2 per-tile test;
         threads: work-group size (0 = the shape's default)."""
         e = _abi.sim_exec(int(tile_rows), int(tile_words), int(depth), int(skip), int(threads))
-        self._check(self._lib.sim_set_exec(self._h, ctypes.byref(e)))
+        with self._on_stream():
+            self._check(self._lib.sim_set_exec(self._h, ctypes.byref(e)))
 
     def get_exec(self):
         e = _abi.sim_exec()
@@ -132,7 +166,8 @@ class Sim:
         """Time every compiled execution shape over T_probe steps from the
         current state (restored afterwards) and keep the fastest."""
         e = _abi.sim_exec()
-        self._check(self._lib.sim_autotune(self._h, int(T_probe), ctypes.byref(e)))
+        with self._on_stream():
+            self._check(self._lib.sim_autotune(self._h, int(T_probe), ctypes.byref(e)))
         return dict(tile_rows=e.tile_rows, tile_words=e.tile_words, depth=e.depth,
                     skip=int(e.skip), threads=int(e.threads))
 
@@ -140,10 +175,18 @@ class Sim:
         self._check(self._lib.sim_use_graphs(self._h, int(bool(on))))
 
     def run(self, T: int):
-        self._check(self._lib.sim_run(self._h, int(T)))
+        with self._on_stream():
+            self._check(self._lib.sim_run(self._h, int(T)))
+
+    def prepare(self, T: int):
+        """Build the propagation table for the next T steps now (run() does it
+        itself when needed)."""
+        with self._on_stream():
+            self._check(self._lib.sim_prepare(self._h, int(T)))
 
     def step(self):
-        self._check(self._lib.sim_step(self._h))
+        with self._on_stream():
+            self._check(self._lib.sim_step(self._h))
 
     @property
     def t(self) -> int:
@@ -155,48 +198,54 @@ class Sim:
         """params: n rows of (p_h, a, c1, c2, p_continue)."""
         rows = [tuple(float(x) for x in r) for r in params]
         arr = (_abi.sim_params * self.n)(*[_abi.sim_params(*r) for r in rows])
-        self._check(self._lib.sim_set_params(self._h, arr))
+        with self._on_stream():
+            self._check(self._lib.sim_set_params(self._h, arr))
         self.p_continue = [float(np.float32(r[4])) for r in rows]
 
     def reset(self, seeds: Optional[Sequence[int]] = None):
-        if seeds is None:
-            self._check(self._lib.sim_reset(self._h, None))
-        else:
+        arr = None
+        if seeds is not None:
             arr = (ctypes.c_uint64 * self.n)(*[int(x) & 0xFFFFFFFFFFFFFFFF for x in seeds])
+        with self._on_stream():
             self._check(self._lib.sim_reset(self._h, arr))
 
     def get_state(self, s: int = 0) -> torch.Tensor:
         H, W = self.shapes[s]
         out = torch.empty((2, H, W), dtype=torch.uint8, device=self.device)
-        self._check(self._lib.sim_get_state(self._h, s, _ptr(out)))
+        with self._on_stream(outputs=[out]):
+            self._check(self._lib.sim_get_state(self._h, s, _ptr(out)))
         return out
 
     def set_state(self, s: int, planes, step: int):
         H, W = self.shapes[s]
-        t = _dev_tensor(planes, torch.uint8, self.device)
-        if tuple(t.shape) != (2, H, W):
-            raise ValueError(f"state must be 2 x {H} x {W}")
-        self._check(self._lib.sim_set_state(self._h, s, _ptr(t), int(step)))
-        self.stream.synchronize()
+        with self._on_stream(inputs=[planes]):
+            t = _dev_tensor(planes, torch.uint8, self.device)
+            if tuple(t.shape) != (2, H, W):
+                raise ValueError(f"state must be 2 x {H} x {W}")
+            self._check(self._lib.sim_set_state(self._h, s, _ptr(t), int(step)))
+            self.stream.synchronize()
 
     def pignite(self, s: int = 0) -> torch.Tensor:
         H, W = self.shapes[s]
         out = torch.empty((H, W), dtype=torch.float32, device=self.device)
-        self._check(self._lib.sim_pignite(self._h, s, _ptr(out)))
+        with self._on_stream(outputs=[out]):
+            self._check(self._lib.sim_pignite(self._h, s, _ptr(out)))
         return out
 
     def accumulator(self, s: int = 0) -> torch.Tensor:
         H, W = self.shapes[s]
         out = torch.empty((H, W), dtype=torch.float32, device=self.device)
-        self._check(self._lib.sim_accumulator(self._h, s, _ptr(out)))
+        with self._on_stream(outputs=[out]):
+            self._check(self._lib.sim_accumulator(self._h, s, _ptr(out)))
         return out
 
     def accumulators(self) -> torch.Tensor:
         """All accumulators concatenated (flat FP32, the adjoint's layout)."""
         out = torch.empty(int(self.offsets[-1]), dtype=torch.float32, device=self.device)
-        for s in range(self.n):
-            a, b = int(self.offsets[s]), int(self.offsets[s + 1])
-            self._check(self._lib.sim_accumulator(self._h, s, _ptr(out[a:b])))
+        with self._on_stream(outputs=[out]):
+            for s in range(self.n):
+                a, b = int(self.offsets[s]), int(self.offsets[s + 1])
+                self._check(self._lib.sim_accumulator(self._h, s, _ptr(out[a:b])))
         return out
 
     def set_adjoint(self, method: str = "checkpoint", rings=None):
@@ -207,58 +256,78 @@ class Sim:
         self._check(self._lib.sim_set_adjoint(self._h, m, rf, rb, rl))
 
     def adjoint(self, dL_dyhat: torch.Tensor) -> torch.Tensor:
-        lam = dL_dyhat.to(device=self.device, dtype=torch.float32).contiguous().view(-1)
-        if lam.numel() != int(self.offsets[-1]):
-            raise ValueError("dL_dyhat must hold every scenario's grid, concatenated")
         grad = torch.empty((self.n, 4), dtype=torch.float64, device=self.device)
-        self._check(self._lib.sim_adjoint(self._h, _ptr(lam), _ptr(grad)))
+        with self._on_stream(inputs=[dL_dyhat], outputs=[grad]):
+            lam = dL_dyhat.to(device=self.device, dtype=torch.float32).contiguous().view(-1)
+            if lam.numel() != int(self.offsets[-1]):
+                raise ValueError("dL_dyhat must hold every scenario's grid, concatenated")
+            self._check(self._lib.sim_adjoint(self._h, _ptr(lam), _ptr(grad)))
         return grad
 
     def loss_grad(self, target, kind: int = _abi.SIM_LOSS_BCE):
-        y = _dev_tensor(target, torch.uint8, self.device).view(-1)
-        if y.numel() != int(self.offsets[-1]):
-            raise ValueError("target must hold every scenario's grid, concatenated")
         loss = torch.empty(self.n, dtype=torch.float64, device=self.device)
         grad = torch.empty((self.n, 4), dtype=torch.float64, device=self.device)
-        self._check(self._lib.sim_loss_grad(self._h, _ptr(y), int(kind), _ptr(loss), _ptr(grad)))
+        with self._on_stream(inputs=[target], outputs=[loss, grad]):
+            y = _dev_tensor(target, torch.uint8, self.device).view(-1)
+            if y.numel() != int(self.offsets[-1]):
+                raise ValueError("target must hold every scenario's grid, concatenated")
+            self._check(self._lib.sim_loss_grad(self._h, _ptr(y), int(kind), _ptr(loss),
+                                                _ptr(grad)))
         return loss, grad
 
     def set_wind(self, s: int, wind_speed=None, wind_dir=None, speed_scalar=0.0, dir_scalar=0.0):
         """New wind for scenario s (fields H x W, or None for the scalars)."""
-        ws = _dev_tensor(wind_speed, torch.float32, self.device)
-        wd = _dev_tensor(wind_dir, torch.float32, self.device)
-        hw = self.shapes[s][0] * self.shapes[s][1] if 0 <= s < self.n else 0
-        for t in (ws, wd):
-            if t is not None and t.numel() != hw:
-                raise ValueError("wind fields must hold H*W values of scenario s")
-        self._check(self._lib.sim_set_wind(self._h, int(s), _ptr(ws), _ptr(wd),
-                                           float(speed_scalar), float(dir_scalar)))
+        with self._on_stream(inputs=[wind_speed, wind_dir]):
+            ws = _dev_tensor(wind_speed, torch.float32, self.device)
+            wd = _dev_tensor(wind_dir, torch.float32, self.device)
+            hw = self.shapes[s][0] * self.shapes[s][1] if 0 <= s < self.n else 0
+            for t in (ws, wd):
+                if t is not None and t.numel() != hw:
+                    raise ValueError("wind fields must hold H*W values of scenario s")
+            self._check(self._lib.sim_set_wind(self._h, int(s), _ptr(ws), _ptr(wd),
+                                               float(speed_scalar), float(dir_scalar)))
 
     def ignite(self, s: int, cells):
         """Spotting: set cells (flat r*W + c indices) burning before the next step."""
-        c = _dev_tensor(np.asarray(cells, dtype=np.int32) if not isinstance(cells, torch.Tensor)
-                        else cells, torch.int32, self.device).view(-1)
-        self._check(self._lib.sim_ignite(self._h, int(s), _ptr(c), int(c.numel())))
+        with self._on_stream(inputs=[cells]):
+            c = _dev_tensor(np.asarray(cells, dtype=np.int32)
+                            if not isinstance(cells, torch.Tensor) else cells,
+                            torch.int32, self.device).view(-1)
+            self._check(self._lib.sim_ignite(self._h, int(s), _ptr(c), int(c.numel())))
 
     def counts(self) -> torch.Tensor:
         """(n, 2) int64 device tensor: burning and burned cells per scenario."""
         out = torch.empty((self.n, 2), dtype=torch.int64, device=self.device)
-        self._check(self._lib.sim_counts(self._h, _ptr(out)))
+        with self._on_stream(outputs=[out]):
+            self._check(self._lib.sim_counts(self._h, _ptr(out)))
         return out
 
     def overlap(self, s: int, target) -> torch.Tensor:
         """(|A & B|, |A | B|) of scenario s's affected cells and a target mask."""
-        y = _dev_tensor(target, torch.uint8, self.device)
-        if not 0 <= s < self.n or y.numel() != self.shapes[s][0] * self.shapes[s][1]:
-            raise ValueError("target must hold H*W values of scenario s")
         out = torch.empty(2, dtype=torch.int64, device=self.device)
-        self._check(self._lib.sim_overlap(self._h, int(s), _ptr(y), _ptr(out)))
+        with self._on_stream(inputs=[target], outputs=[out]):
+            y = _dev_tensor(target, torch.uint8, self.device)
+            if not 0 <= s < self.n or y.numel() != self.shapes[s][0] * self.shapes[s][1]:
+                raise ValueError("target must hold H*W values of scenario s")
+            self._check(self._lib.sim_overlap(self._h, int(s), _ptr(y), _ptr(out)))
         return out
 
     def jaccard(self, s: int, target) -> float:
         """Eq. 11 against a target affected-area mask."""
         i, u = (int(x) for x in self.overlap(s, target).cpu())
         return 1.0 if u == 0 else i / u
+
+    def metrics(self, targets) -> torch.Tensor:
+        """(n, 4) int64 device tensor: per scenario (|A & B|, |A | B|, |A|, |B|)
+        of its affected cells A and its observed map B (``targets``: the n
+        grids concatenated) -- the inputs of Eq. 11 and Eq. 12."""
+        out = torch.empty((self.n, 4), dtype=torch.int64, device=self.device)
+        with self._on_stream(inputs=[targets], outputs=[out]):
+            y = _dev_tensor(targets, torch.uint8, self.device).view(-1)
+            if y.numel() != int(self.offsets[-1]):
+                raise ValueError("targets must hold every scenario's grid, concatenated")
+            self._check(self._lib.sim_metrics(self._h, _ptr(y), _ptr(out)))
+        return out
 
     def arrival(self, s0: int = 0, n: Optional[int] = None, counts=None) -> torch.Tensor:
         """Add, per cell, the number of scenarios s0 .. s0+n-1 (one grid shape)
@@ -272,7 +341,8 @@ class Sim:
             counts = torch.zeros((H, W), dtype=torch.int32, device=self.device)
         if counts.dtype != torch.int32 or counts.numel() != H * W or not counts.is_contiguous():
             raise ValueError("counts must be a contiguous int32 tensor of H*W cells")
-        self._check(self._lib.sim_arrival(self._h, int(s0), n, _ptr(counts)))
+        with self._on_stream(inputs=[counts], outputs=[counts]):
+            self._check(self._lib.sim_arrival(self._h, int(s0), n, _ptr(counts)))
         return counts
 
     def tie_log(self):
@@ -281,11 +351,12 @@ class Sim:
         cell, p_ignite, draw, ignited, sorted by (scenario, step, cell); and the
         number of trials logged (more than the records if the log overflowed)."""
         n = ctypes.c_int64()
-        self._check(self._lib.sim_tielog(self._h, None, 0, ctypes.byref(n)))
-        m = min(int(n.value), _abi.SIM_TIELOG_CAP)
-        buf = torch.empty(max(m, 1) * ctypes.sizeof(_abi.sim_tie), dtype=torch.uint8,
-                          device=self.device)
-        self._check(self._lib.sim_tielog(self._h, _ptr(buf), m, ctypes.byref(n)))
+        with self._on_stream():
+            self._check(self._lib.sim_tielog(self._h, None, 0, ctypes.byref(n)))
+            m = min(int(n.value), _abi.SIM_TIELOG_CAP)
+            buf = torch.empty(max(m, 1) * ctypes.sizeof(_abi.sim_tie), dtype=torch.uint8,
+                              device=self.device)
+            self._check(self._lib.sim_tielog(self._h, _ptr(buf), m, ctypes.byref(n)))
         dt = np.dtype([("scenario", "<i4"), ("step", "<i4"), ("cell", "<i8"),
                        ("p_ignite", "<f4"), ("draw", "<f4"), ("ignited", "<i4"),
                        ("reserved", "<i4")])

@@ -551,3 +551,43 @@ def test_run_ties_lists_the_ties_of_each_step(oracle_lib):
     assert len(want) > 5 and r["ties"] == len(want)
     assert list(zip(r["tie_step"].tolist(), r["tie_cell"].tolist())) == want
     assert np.array_equal(r["S"], S)
+
+
+# ------------------------------------------------------------ Algorithm 1
+
+def test_adamw_matches_torch_cpu(oracle_lib):
+    """The oracle's AdamW (decoupled weight decay) reproduces torch's CPU
+    AdamW in FP64 step for step, with the paper's lr and torch's defaults."""
+    import torch
+    rng = np.random.default_rng(3)
+    th0 = rng.uniform(0.1, 0.9, 4)
+    ref = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.AdamW([ref], lr=5e-3)
+    mine = oracle_lib.AdamW(th0, lr=5e-3)
+    for _ in range(12):
+        g = rng.standard_normal(4) * rng.uniform(1e-3, 10.0)
+        ref.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        mine.step(g)
+        np.testing.assert_allclose(mine.theta, ref.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+def test_algorithm1_sequence_clamps_and_metrics(oracle_lib):
+    """Oracle Algorithm 1: parameters stay in the clamp box, the first
+    iteration's gradient is the analytic gradient at theta0, Jaccard equals
+    1 and Manhattan 0 when the observations are the run's own states."""
+    s = synth.make_lakes(48, 40, 71, T=30, n_ignitions=2)
+    th0 = [0.58, 0.078, 0.045, 0.131]
+    base = s.with_params(*th0)
+    obs = [(oracle_lib.run(dataclasses.replace(base, seed=1000), 10 * (k + 1))["S"] != 0)
+           .astype(np.uint8).ravel() for k in range(3)]
+    hist = oracle_lib.calibrate_sequence(s, obs, th0, interval=10, epochs=1, lr=1e-2)
+    assert [h["iteration"] for h in hist] == [0, 1, 2]
+    r0 = oracle_lib.run(dataclasses.replace(base, seed=1000), 10, want_yhat=True)
+    L, lam = oracle_lib.loss(r0["yhat"], obs[0].reshape(s.H, s.W), 0)
+    assert hist[0]["loss"] == L
+    np.testing.assert_array_equal(hist[0]["grad"],
+                                  oracle_lib.grad(dataclasses.replace(base, seed=1000), 10, lam))
+    assert hist[0]["jaccard"] == 1.0 and hist[0]["manhattan"] == 0
+    for h in hist:
+        assert np.all(h["theta"] >= oracle_lib.CLAMP_LO) and np.all(h["theta"] <= oracle_lib.CLAMP_HI)
