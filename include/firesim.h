@@ -157,6 +157,32 @@ SIM_API int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* w
              size_t ws_bytes, void* stream, uint32_t flags, int32_t ckpt_every,
              int32_t T_max);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): sim_init without a
+ * workspace argument.  The handle's workspace is a 128 MiB array in the
+ * library's static device memory, one copy per GPU, which that GPU holds
+ * from the first call on it until the process ends.  The call allocates
+ * nothing on the device (no hipMalloc, no allocating library routine); the
+ * caller still owns the fields and every output buffer.
+ *   - Size: scenarios whose sim_workspace_size exceeds
+ *     SIM_STATIC_SCRATCH_BYTES are rejected with SIM_E_WORKSPACE (nothing is
+ *     enqueued).  One scenario fits up to about 1280 x 1280 cells (forward)
+ *     or 1120 x 1120 (calibration, 200 steps, checkpoints every 20).
+ *   - One static handle per GPU at a time: the array is the handle's whole
+ *     workspace, so while one exists on the current device another
+ *     sim_init_static there returns SIM_E_STATE.  sim_destroy of a static
+ *     handle waits for its stream, then releases the array.
+ *   - The array keeps what the last handle left in it; set-up initialises
+ *     every part the kernels read, exactly as sim_init does for a reused
+ *     workspace.  Work enqueued by a destroyed handle's caller on other
+ *     streams after sim_destroy must not touch the array.
+ *   - The device is the current HIP device at the call; `stream` must belong
+ *     to it.  Arguments, flags, errors and the behaviour of every other call
+ *     on the handle are those of sim_init. */
+#define SIM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+SIM_API int sim_init_static(sim_handle** out, const sim_desc* descs, int32_t n, void* stream,
+                            uint32_t flags, int32_t ckpt_every, int32_t T_max);
+
 /* Choose the execution shape (default: 32 rows x 2 words, depth 32, worklist skipping;
  * sim_autotune picks one by timing).  Only whitelisted shapes are compiled; others give
  * SIM_E_SHAPE. */
@@ -310,7 +336,9 @@ SIM_API int sim_stats(sim_handle* h, uint64_t out[4]);
 /* Last error message of `h` (or of the last failed sim_init when h is NULL). */
 SIM_API const char* sim_last_error(const sim_handle* h);
 
-/* Release the handle (host memory only; the caller frees the workspace). */
+/* Release the handle (host memory only; the caller frees the workspace).  A
+ * handle from sim_init_static first waits for its stream, then gives the
+ * device's static scratch back. */
 SIM_API void sim_destroy(sim_handle* h);
 
 /* Library version string. */

@@ -24,6 +24,7 @@ SIM_F_CALIB = 1
 SIM_F_STATS = 2
 SIM_F_TIELOG = 4
 SIM_TIELOG_CAP = 1 << 20
+SIM_STATIC_SCRATCH_BYTES = 128 << 20
 
 SIM_LOSS_BCE = 0
 SIM_LOSS_BCE_MSE = 1
@@ -75,7 +76,7 @@ EXPORTS = (
     "sim_pignite", "sim_accumulator", "sim_adjoint", "sim_loss_grad", "sim_stats",
     "sim_last_error", "sim_destroy", "sim_version", "sim_autotune", "sim_use_graphs",
     "sim_set_adjoint", "sim_set_wind", "sim_ignite", "sim_counts", "sim_overlap", "sim_arrival", "sim_tielog",
-    "sim_metrics", "sim_prepare",
+    "sim_metrics", "sim_prepare", "sim_init_static",
 )
 
 _lib = None
@@ -100,6 +101,8 @@ def load():
         "sim_workspace_size": (sz, [ctypes.POINTER(sim_desc), i32, u32, i32, i32]),
         "sim_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(sim_desc), i32, vp, sz,
                                     vp, u32, i32, i32]),
+        "sim_init_static": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(sim_desc), i32,
+                                           vp, u32, i32, i32]),
         "sim_set_exec": (ctypes.c_int, [H, ctypes.POINTER(sim_exec)]),
         "sim_get_exec": (ctypes.c_int, [H, ctypes.POINTER(sim_exec)]),
         "sim_run": (ctypes.c_int, [H, i32]),

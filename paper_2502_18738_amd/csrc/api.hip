@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -246,6 +247,7 @@ struct sim_handle {
     std::vector<int32_t> ib0;       // blocks of the state-reset kernel per scenario (prefix)
     std::vector<int64_t> cell0;
     hipStream_t cap = nullptr;      // private stream used only for capture
+    int static_dev = -1;            // device whose static scratch this handle holds (-1: none)
 
     void drop_graphs() {
         for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
@@ -388,8 +390,13 @@ size_t sim_workspace_size(const sim_desc* descs, int32_t n, uint32_t flags, int3
     return L.total;
 }
 
-int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace,
-             size_t ws_bytes, void* stream, uint32_t flags, int32_t ckpt_every, int32_t T_max) {
+}  // extern "C"
+
+namespace {
+
+// Checks shared by sim_init and sim_init_static (before any GPU work).
+int check_init_args(sim_handle** out, const sim_desc* descs, int32_t n, uint32_t flags,
+                    int32_t ckpt_every, int32_t T_max) {
     g_init_error.clear();
     if (!out) { g_init_error = "out is NULL"; return SIM_E_ARG; }
     *out = nullptr;
@@ -404,11 +411,16 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
         g_init_error = "calibration mode needs ckpt_every >= 1 and T_max >= 1";
         return SIM_E_SHAPE;
     }
-    if (!workspace) { g_init_error = "workspace is NULL"; return SIM_E_ARG; }
-    if ((uintptr_t)workspace % kAlign) {
-        g_init_error = "workspace must be 256-byte aligned";
-        return SIM_E_WORKSPACE;
-    }
+    return SIM_OK;
+}
+
+// Handle set-up over a checked workspace (the caller's, or a device's static
+// scratch): carves the workspace, builds the per-cell records, slope table,
+// fuel plane and initial state, and reads the validation flag.
+int init_handle(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace,
+                size_t ws_bytes, void* stream, uint32_t flags, int32_t ckpt_every,
+                int32_t T_max) {
+    int rc = SIM_OK;
     sim_handle* h = new (std::nothrow) sim_handle();
     if (!h) { g_init_error = "out of host memory"; return SIM_E_ARG; }
     h->n = n;
@@ -555,6 +567,99 @@ int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace
         return rc;
     }
     *out = h;
+    return SIM_OK;
+}
+
+// Scratch of sim_init_static: the workspace of the one static handle a device
+// may hold at a time.  In host code `scratch` names a host-side stand-in, not
+// device memory: every host use goes through the per-device address that
+// hipGetSymbolAddress returns (g_static.ptr), never through the name.
+constexpr size_t kStaticScratchBytes = SIM_STATIC_SCRATCH_BYTES;
+__device__ __align__(256) char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+struct StaticSlots {
+    std::mutex mu;
+    void* ptr[kMaxDevices] = {};      // device address of `scratch` on each device
+    bool held[kMaxDevices] = {};      // a live static handle uses that device's array
+} g_static;
+
+void release_static(sim_handle* h) {
+    if (!h || h->static_dev < 0) return;
+    std::lock_guard<std::mutex> lk(g_static.mu);
+    g_static.held[h->static_dev] = false;
+    h->static_dev = -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_init(sim_handle** out, const sim_desc* descs, int32_t n, void* workspace,
+             size_t ws_bytes, void* stream, uint32_t flags, int32_t ckpt_every, int32_t T_max) {
+    int rc = check_init_args(out, descs, n, flags, ckpt_every, T_max);
+    if (rc) return rc;
+    if (!workspace) { g_init_error = "workspace is NULL"; return SIM_E_ARG; }
+    if ((uintptr_t)workspace % kAlign) {
+        g_init_error = "workspace must be 256-byte aligned";
+        return SIM_E_WORKSPACE;
+    }
+    return init_handle(out, descs, n, workspace, ws_bytes, stream, flags, ckpt_every, T_max);
+}
+
+int sim_init_static(sim_handle** out, const sim_desc* descs, int32_t n, void* stream,
+                    uint32_t flags, int32_t ckpt_every, int32_t T_max) {
+    int rc = check_init_args(out, descs, n, flags, ckpt_every, T_max);
+    if (rc) return rc;
+    Layout L;
+    plan(descs, n, flags, ckpt_every, T_max, &L);
+    if (L.total > kStaticScratchBytes) {
+        char buf[200];
+        snprintf(buf, sizeof buf, "these scenarios need %zu bytes of workspace; the static "
+                 "scratch holds %zu (use sim_init with a workspace)", L.total,
+                 kStaticScratchBytes);
+        g_init_error = buf;
+        return SIM_E_WORKSPACE;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        g_init_error = "no current HIP device (or device index >= 64)";
+        return SIM_E_HIP;
+    }
+    void* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static.mu);
+        if (g_static.held[dev]) {
+            g_init_error = "the static scratch of this device is held by another handle "
+                           "(sim_destroy it first)";
+            return SIM_E_STATE;
+        }
+        if (!g_static.ptr[dev]) {
+            // once per device, with that device current: the address of this
+            // device's copy of the array
+            void* p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p) {
+                g_init_error = std::string("hipGetSymbolAddress(scratch): ") +
+                               hipGetErrorString(e);
+                return SIM_E_HIP;
+            }
+            if ((uintptr_t)p % kAlign) {
+                g_init_error = "static scratch is not 256-byte aligned";
+                return SIM_E_WORKSPACE;
+            }
+            g_static.ptr[dev] = p;
+        }
+        ws = g_static.ptr[dev];
+        g_static.held[dev] = true;
+    }
+    rc = init_handle(out, descs, n, ws, kStaticScratchBytes, stream, flags, ckpt_every, T_max);
+    if (rc) {
+        std::lock_guard<std::mutex> lk(g_static.mu);
+        g_static.held[dev] = false;
+        return rc;
+    }
+    (*out)->static_dev = dev;
     return SIM_OK;
 }
 
@@ -1194,6 +1299,15 @@ const char* sim_last_error(const sim_handle* h) {
     return h ? h->err.c_str() : g_init_error.c_str();
 }
 
-void sim_destroy(sim_handle* h) { delete h; }
+void sim_destroy(sim_handle* h) {
+    if (!h) return;
+    if (h->static_dev >= 0) {
+        // the next static handle on this device reuses the array: let this
+        // handle's queued work finish before the array is handed out again
+        (void)hipStreamSynchronize(h->st);
+        release_static(h);
+    }
+    delete h;
+}
 
 }  // extern "C"

@@ -43,7 +43,8 @@ class Sim:
     def __init__(self, scenarios: Sequence, *, device="cuda", calib: bool = False,
                  stats: bool = False, ckpt_every: int = 20, T_max: Optional[int] = None,
                  tielog: bool = False,
-                 exec: Optional[dict] = None, stream: Optional[torch.cuda.Stream] = None):
+                 exec: Optional[dict] = None, stream: Optional[torch.cuda.Stream] = None,
+                 static_scratch: bool = False):
         self._lib = _abi.load()
         self.device = torch.device(device)
         self.n = len(scenarios)
@@ -58,6 +59,10 @@ class Sim:
         T_max = int(T_max or 0)
         self._keep = []
         self._h = None
+        # static_scratch: the handle's workspace is the library's static array
+        # on this device (sim_init_static), so construction allocates no
+        # workspace; at most one such handle per device at a time
+        self.static_scratch = bool(static_scratch)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with self._on_stream():
             self._init(scenarios, flags, int(ckpt_every), T_max)
@@ -91,16 +96,23 @@ class Sim:
                                      int(s.scenario_id) & 0xFFFFFFFF,
                                      int(s.seed) & 0xFFFFFFFFFFFFFFFF, par, fields)
         self._descs = descs
-        nbytes = self._lib.sim_workspace_size(descs, self.n, flags, int(ckpt_every), T_max)
-        if nbytes == 0:
-            raise SimError(_abi.SIM_E_ARG, "invalid scenario descriptions")
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        aligned = (base + 255) & ~255
         h = ctypes.c_void_p()
-        rc = self._lib.sim_init(ctypes.byref(h), descs, self.n, ctypes.c_void_p(aligned), nbytes,
-                                ctypes.c_void_p(self.stream.cuda_stream), flags,
-                                int(ckpt_every), T_max)
+        if self.static_scratch:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                rc = self._lib.sim_init_static(ctypes.byref(h), descs, self.n,
+                                               ctypes.c_void_p(self.stream.cuda_stream), flags,
+                                               int(ckpt_every), T_max)
+        else:
+            nbytes = self._lib.sim_workspace_size(descs, self.n, flags, int(ckpt_every), T_max)
+            if nbytes == 0:
+                raise SimError(_abi.SIM_E_ARG, "invalid scenario descriptions")
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            aligned = (base + 255) & ~255
+            rc = self._lib.sim_init(ctypes.byref(h), descs, self.n, ctypes.c_void_p(aligned),
+                                    nbytes, ctypes.c_void_p(self.stream.cuda_stream), flags,
+                                    int(ckpt_every), T_max)
         if rc != 0:
             raise SimError(rc, self._lib.sim_last_error(None).decode())
         self._h = h

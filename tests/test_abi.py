@@ -114,3 +114,18 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.sim_get_state(None, 0, None) == _abi.SIM_E_ARG
     assert lib.sim_adjoint(None, None, None) == _abi.SIM_E_ARG
     lib.sim_destroy(None)
+
+
+def test_init_static_rejects_before_any_gpu_work(lib):
+    """Size and argument checks of sim_init_static run on the host first."""
+    h = ctypes.c_void_p()
+    big = (_abi.sim_desc * 1)(fake_desc(H=1400, W=1400))
+    assert lib.sim_workspace_size(big, 1, 0, 0, 0) > _abi.SIM_STATIC_SCRATCH_BYTES
+    rc = lib.sim_init_static(ctypes.byref(h), big, 1, None, 0, 0, 0)
+    assert rc == _abi.SIM_E_WORKSPACE and not h.value
+    assert "static scratch" in lib.sim_last_error(None).decode()
+    small = (_abi.sim_desc * 1)(fake_desc())
+    assert lib.sim_init_static(ctypes.byref(h), small, 1, None, 0x80, 0, 0) == _abi.SIM_E_ARG
+    assert lib.sim_init_static(ctypes.byref(h), small, 1, None, _abi.SIM_F_CALIB, 0, 10) \
+        == _abi.SIM_E_SHAPE
+    assert lib.sim_init_static(None, small, 1, None, 0, 0, 0) == _abi.SIM_E_ARG
