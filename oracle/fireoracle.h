@@ -66,7 +66,8 @@ void fo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
 void fo_draws(const fo_problem* pb, int32_t t, int64_t cell, double* u_ign, double* u_cont);
 
 /* f_p(p_propagate) of Eq. 2-5 for a burning neighbour at (r+dr, c+dc)
- * spreading into cell (r, c).  Optional outputs: theta_s (deg), cos(delta). */
+ * spreading into cell (r, c); both cells must lie inside the grid (cells
+ * outside it never burn).  Optional outputs: theta_s (deg), cos(delta). */
 double fo_edge_q(const fo_problem* pb, int32_t r, int32_t c, int32_t dr, int32_t dc,
                  double* theta_s_out, double* cosd_out);
 
