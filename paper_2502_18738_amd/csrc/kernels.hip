@@ -183,8 +183,13 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
 // this routine, so they agree cell by cell.
 // The table rows of cell j (rec and th8 entries) are passed in, so that a
 // caller can issue their reads early.
-__device__ __forceinline__ void pignite_grad_tab(const DevScen& J, float4 rec, fs_f4 ta, fs_f4 tb,
-                                                 uint32_t sm, const float q[8], float gl[4]) {
+struct EdgeParams {
+    float p_h, a, c1, c2, c;
+};
+
+__device__ __forceinline__ void pignite_grad_tab(const EdgeParams& J, float4 rec, fs_f4 ta,
+                                                 fs_f4 tb, uint32_t sm, const float q[8],
+                                                 float gl[4]) {
     const float th[8] = {ta.x, ta.y, ta.z, ta.w, tb.x, tb.y, tb.z, tb.w};
     float pre[8], suf[8], acc = 1.f;
 #pragma unroll
@@ -231,37 +236,6 @@ __device__ __forceinline__ int block_exscan(int v, int* sWave, int* total) {
     return pre + x - v;
 }
 
-// Exclusive prefix sums of two per-thread values over the work-group in one
-// pass (sWave holds 2 * NWAVE ints); returns the prefix of v, sets the prefix
-// of u and both totals.  Ends without a barrier: the caller must synchronise
-// before sWave is written again.
-template <int NWAVE>
-__device__ __forceinline__ int block_exscan2(int v, int u, int* sWave, int* tot_v, int* pre_u,
-                                             int* tot_u) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int x = wave_incl_scan(v), y = wave_incl_scan(u);
-    if (lane == 63) {
-        sWave[wv] = x;
-        sWave[NWAVE + wv] = y;
-    }
-    __syncthreads();
-    int pv = 0, tv = 0, pu = 0, tu = 0;
-#pragma unroll
-    for (int k = 0; k < NWAVE; ++k) {
-        const int s = sWave[k], t = sWave[NWAVE + k];
-        if (k < wv) {
-            pv += s;
-            pu += t;
-        }
-        tv += s;
-        tu += t;
-    }
-    *tot_v = tv;
-    *tot_u = tu;
-    *pre_u = pu + y - u;
-    return pv + x - v;   // the caller barriers before sWave is written again
-}
-
 // XCD-aware tile order: consecutive workgroups are dealt round-robin to the 8
 // XCDs, so give XCD x a contiguous run of tiles (neighbouring tiles share
 // halo rows in that XCD's L2).
@@ -299,11 +273,13 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     // burning plane ping-pong: sB[cur] = S(t-1), sB[cur ^ 1] collects the
     // successful trials of step t, which are exactly the burning cells of S(t).
     // The burned plane of a word lives in its owner thread's registers.
-    __shared__ uint32_t sB[2][NW], sU[NW];
+    __shared__ uint32_t sB[2][NW];
     __shared__ uint16_t sL[LCAP];
-    // words holding a trial this step: (word index, trial mask, ignition
-    // mask, offset of the word's first list entry)
-    __shared__ uint4 sWL[NW];
+    // words holding a trial this step, one segment per wavefront (its lanes'
+    // words in lane order): (word index, trial mask, ignition mask, offset of
+    // the word's first list entry within the wavefront's trials)
+    constexpr int SEG = 64 * WPT;
+    __shared__ uint4 sWL[NWAVE * SEG];
     // per word, which of the 8 neighbour slots of each of its 32 cells burn
     // (one mask per slot), written for words with ignition trials by the
     // 512-lane shapes; the others rebuild an ignition trial's masks from the
@@ -406,11 +382,13 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     const int w0 = tcol * TC - 1;
     uint32_t origB[WPT], origD[WPT];
     uint32_t dreg[WPT], bprev[WPT];   // burned plane; burning plane one step back
+    uint32_t ureg[WPT];               // fuel plane (constant)
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
         const int w = tid + i * NT;
         origB[i] = origD[i] = 0;
         dreg[i] = bprev[i] = 0;
+        ureg[i] = 0;
         if (w < NW) {
             const int lr = w / RC, lc = w - (w / RC) * RC;
             const int gr = r0 + lr, gw = w0 + lc;
@@ -422,7 +400,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 u = fuel[o];
             }
             sB[0][w] = b;
-            sU[w] = u;
+            ureg[i] = u;
             origB[i] = b;
             origD[i] = d;
         }
@@ -435,13 +413,23 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     }
 
     const uint32_t k0s = J.seed_lo, k1s = J.seed_hi, scen = J.scen_id;
+    // fields every step reads, held in registers: after each work-group
+    // barrier (an acquire fence) the compiler would reload them from memory
+    // (the calibration and tie-log pointers, read only on some trials, are
+    // left in the descriptor to keep scalar registers free; only whether
+    // they are present is kept)
+    const int Wg = J.W, t_base = J.t_base;
+    const float p_cont = J.p_continue;
+    // (adjoint recompute jobs never write the maps or the tie log)
+    const bool has_yhat = !ADJ && J.yhat != nullptr, has_tign = !ADJ && J.tign != nullptr,
+               has_tout = !ADJ && J.tout != nullptr, has_tlog = !ADJ && J.tielog != nullptr;
     double gsum[4] = {0.0, 0.0, 0.0, 0.0};
     unsigned long long n_trials = 0, n_ties = 0;
     int cur = 0;
 
     for (int s = 1; s <= kj; ++s) {
         __syncthreads();
-        const int t = J.t_base + t_off + s;
+        const int t = t_base + t_off + s;
         // cells still needed: rows and halo-word bits within kj - s cells of
         // the tile (they are also the ones whose inputs are still valid; trials
         // farther out could not reach the tile before the launch ends)
@@ -505,7 +493,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     bprev[i] = mid;
                     const uint32_t keep = lc == 0 ? keepL : (lc == RC - 1 ? keepR : ~0u);
                     mc[i] = mid & keep;
-                    mi[i] = nbm & ~mid & ~dreg[i] & sU[w] & keep;
+                    mi[i] = nbm & ~mid & ~dreg[i] & ureg[i] & keep;
                     cnt += __popc(mc[i] | mi[i]);
                     nne += (mc[i] | mi[i]) != 0u;
                     nR[w] = 0;
@@ -518,24 +506,22 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 }
             }
         }
-        int tot, pre_w, tot_w;
-        const int off = block_exscan2<NWAVE>(cnt, nne, sWave, &tot, &pre_w, &tot_w);
-        // (a scalar: the branches on it below are uniform)
-        const int ntr = __builtin_amdgcn_readfirstlane(tot);
-        if (ntr == 0) {
-            // no trial within reach of the tile: no cell of the band burns or
-            // can ignite, so the band stays as it is for the rest of the launch
-            cur ^= 1;
-            break;
-        }
-
-        // compacted trial list in word order, bit 15 of an entry marking an
-        // ignition trial (else a continue trial): the words with trials are
-        // listed first, then 8 lanes per listed word place its set bits, 4
-        // bits each (rank = popcount below the bit), so a busy word costs
-        // little more than a quiet one
+        // compacted trial list in thread order (the words of a thread in
+        // index order), bit 15 of an entry marking an ignition trial (else a
+        // continue trial).  Each wavefront lists its busy words in its own
+        // segment of sWL before the work-group barrier, with offsets within
+        // the wavefront (DPP scans); after the barrier the wavefronts' totals
+        // give the work-group prefixes, and 8 lanes per listed word place its
+        // set bits, 4 bits each (rank = popcount below the bit), so a busy
+        // word costs little more than a quiet one
+        // The two counts share one scan: trials in the low 16 bits, busy words
+        // in the high 16 (a region has at most 32 768 cells, so neither half
+        // overflows, per wavefront or per work-group).
+        const int lane = tid & 63, wv = tid >> 6;
         {
-            int oc = off, k = pre_w;
+            const int packed = cnt | (nne << 16);
+            const int xp = wave_incl_scan(packed);
+            int oc = (xp & 0xFFFF) - cnt, k = wv * SEG + (xp >> 16) - nne;
 #pragma unroll
             for (int i = 0; i < WPT; ++i) {
                 const uint32_t mm = mc[i] | mi[i];
@@ -545,23 +531,54 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     oc += __popc(mm);
                 }
             }
+            if (lane == 63) sWave[wv] = xp;
         }
         __syncthreads();
+        // work-group prefixes of the wavefronts' trials (tp) and busy words (bp)
+        int tp[NWAVE], bp[NWAVE];
+        int acc = 0;
+#pragma unroll
+        for (int v = 0; v < NWAVE; ++v) {
+            tp[v] = acc & 0xFFFF;
+            bp[v] = acc >> 16;
+            acc += sWave[v];
+        }
+        const int tot = acc & 0xFFFF, tot_w = acc >> 16;
+        // (a scalar: the branches on it below are uniform).  A step without
+        // trials has no busy word either; testing both keeps every read of
+        // the wavefront totals ahead of the branch (one LDS round trip).
+        const int ntr = __builtin_amdgcn_readfirstlane(tot);
+        if (ntr == 0 && __builtin_amdgcn_readfirstlane(tot_w) == 0) {
+            // no trial within reach of the tile: no cell of the band burns or
+            // can ignite, so the band stays as it is for the rest of the launch
+            cur ^= 1;
+            break;
+        }
+
         for (int x = tid; x < tot_w * 8; x += NT) {
-            // lane x & 7 of a listed word places the trials among its bits
-            // 4 (x & 7) .. 4 (x & 7) + 3
-            const uint4 wl = sWL[x >> 3];
+            // lane x & 7 of listed word k = x >> 3 places the trials among its
+            // bits 4 (x & 7) .. 4 (x & 7) + 3; the word sits in the segment of
+            // the last wavefront whose prefix does not exceed k
+            const int k = x >> 3;
+            int seg = 0, kb = 0, tb = 0;
+#pragma unroll
+            for (int v = 1; v < NWAVE; ++v) {
+                if (k >= bp[v]) {
+                    seg = v;
+                    kb = bp[v];
+                    tb = tp[v];
+                }
+            }
+            const uint4 wl = sWL[seg * SEG + (k - kb)];
             const int b0 = (x & 7) * 4;
             const uint32_t m = (wl.y >> b0) & 15u;
-            if (m) {
-                int pos = wl.w + __popc(wl.y & ((1u << b0) - 1u));
+            int pos = tb + (int)wl.w + __popc(wl.y & ((1u << b0) - 1u));
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if ((m >> q) & 1u) {
-                        const int b = b0 + q;
-                        sL[pos] = (uint16_t)((wl.x * 32 + b) | (((wl.z >> b) & 1u) ? 0x8000u : 0u));
-                        ++pos;
-                    }
+            for (int q = 0; q < 4; ++q) {
+                if ((m >> q) & 1u) {
+                    const int b = b0 + q;
+                    sL[pos] = (uint16_t)((wl.x * 32 + b) | (((wl.z >> b) & 1u) ? 0x8000u : 0u));
+                    ++pos;
                 }
             }
         }
@@ -581,10 +598,9 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             constexpr int R = 1;
             const bool att = ADJ && attached(rings, t);
             const FS_GLOBAL fs_f4* q8v = (const FS_GLOBAL fs_f4*)q8g;
-            const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
             // flat index of the region's top-left cell (may be negative; every
             // listed cell lies inside the grid)
-            const int64_t jbase = (int64_t)r0 * J.W + (int64_t)w0 * 32;
+            const int64_t jbase = (int64_t)r0 * Wg + (int64_t)w0 * 32;
             for (int k0 = 0; k0 < ntr; k0 += R * NT) {
                 int ent[R], ign[R];
                 fs_f4 qa[R], qb[R];
@@ -607,11 +623,13 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     if (k < ntr && ign[r]) {
                         const int w = ent[r] >> 5, bit = ent[r] & 31;
                         const int lr = w / RC, lc = w - (w / RC) * RC;
-                        const int64_t j = jbase + (lr * J.W + lc * 32 + bit);
+                        const int64_t j = jbase + (lr * Wg + lc * 32 + bit);
                         qa[r] = q8v[2 * j];
                         qb[r] = q8v[2 * j + 1];
                         if constexpr (ADJ) {
                             if (att && lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC) {
+                                // (adjoint-only fields: read where used)
+                                const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
                                 ta[r] = t8v[2 * j];
                                 tb[r] = t8v[2 * j + 1];
                                 rc[r] = load_f4(J.rec, j);
@@ -627,15 +645,15 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     if (k >= ntr) continue;
                     const int w = ent[r] >> 5, bit = ent[r] & 31;
                     const int lr = w / RC, lc = w - (w / RC) * RC;
-                    const int64_t j = jbase + (lr * J.W + lc * 32 + bit);
+                    const int64_t j = jbase + (lr * Wg + lc * 32 + bit);
                     const bool interior = lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC;
                     uint32_t rw0, rw1;
                     philox_w01((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, scen,
                                k0s, k1s, rw0, rw1);
                     if (!ign[r]) {  // burning: continue trial
-                        if (u24(rw1) < J.p_continue) {
+                        if (u24(rw1) < p_cont) {
                             atomicOr(&nR[w], 1u << bit);
-                        } else if (interior && J.tout) {
+                        } else if (interior && has_tout) {
                             gmem(J.tout)[j] = t;
                         }
                         if (interior) ++n_trials;
@@ -681,15 +699,16 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     const float u = u24(rw0);
                     if (u < P) {
                         atomicOr(&nR[w], 1u << bit);
-                        if (interior && J.yhat) gmem(J.yhat)[j] = P;
-                        if (interior && J.tign) gmem(J.tign)[j] = t;
+                        if (interior && has_yhat) gmem(J.yhat)[j] = P;
+                        if (interior && has_tign) gmem(J.tign)[j] = t;
                         if constexpr (ADJ) {
                             if (interior && att) {
                                 uint32_t sm = 0;   // burning slots
 #pragma unroll
                                 for (int m = 0; m < 8; ++m) sm |= ((nm[m] >> bit) & 1u) << m;
                                 float gl[4];
-                                pignite_grad_tab(J, rc[r], ta[r], tb[r], sm, q, gl);
+                                pignite_grad_tab(EdgeParams{J.p_h, J.a, J.c1, J.c2, J.c}, rc[r],
+                                                 ta[r], tb[r], sm, q, gl);
 #pragma unroll
                                 for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj[r] * gl[m]);
                             }
@@ -698,7 +717,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     if (interior) {
                         ++n_trials;
                         if (fabsf(u - P) <= kTieEps) ++n_ties;
-                        if (!ADJ && J.tielog && fabsf(u - P) <= kTieLogEps) {
+                        if (!ADJ && has_tlog && fabsf(u - P) <= kTieLogEps) {
                             const unsigned long long n = atomicAdd(J.tie_n, 1ull);
                             if (n < (unsigned long long)kTieLogCap) {
                                 FS_GLOBAL TieRec* tr = gmem(reinterpret_cast<TieRec*>(J.tielog)) + n;
@@ -1283,7 +1302,8 @@ k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0
             for (int m = 0; m < 8; ++m) q[m] = ((sm >> m) & 1u) ? qv[m] : 0.f;
             const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
             float gl[4];
-            pignite_grad_tab(J, load_f4(J.rec, j), t8v[2 * j], t8v[2 * j + 1], sm, q, gl);
+            pignite_grad_tab(EdgeParams{J.p_h, J.a, J.c1, J.c2, J.c}, load_f4(J.rec, j),
+                             t8v[2 * j], t8v[2 * j + 1], sm, q, gl);
             const float lj = lam[J.lam_off + j];
 #pragma unroll
             for (int m = 0; m < 4; ++m) g[m] = (double)(lj * gl[m]);
