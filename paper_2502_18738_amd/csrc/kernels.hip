@@ -34,6 +34,12 @@ constexpr float kSqrtHalf = 0.70710678118654752440f;
 constexpr float kTwoM24 = 5.9604644775390625e-08f;  // 2^-24
 constexpr float kTieEps = 1e-5f;
 
+// Three-input XOR in one VALU instruction (gfx950 v_bitop3_b32, truth
+// table 0x96 = a ^ b ^ c); the key operand may be a scalar register.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon et al., SC'11): returns words 0 and 1.
 __device__ __forceinline__ void philox_w01(uint32_t c0, uint32_t c1, uint32_t c2,
                                            uint32_t c3, uint32_t k0, uint32_t k1,
@@ -43,9 +49,16 @@ __device__ __forceinline__ void philox_w01(uint32_t c0, uint32_t c1, uint32_t c2
         // one 32 x 32 -> 64-bit product per multiplier gives both halves
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        if (i < 2) {
+            // the callers' step and scenario words are uniform, so part of the
+            // first two rounds stays in scalar registers: plain XORs there
+            c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+            c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        } else {
+            c0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+            c2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        }
         c1 = (uint32_t)p1;
-        c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -423,6 +436,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     // (adjoint recompute jobs never write the maps or the tie log)
     const bool has_yhat = !ADJ && J.yhat != nullptr, has_tign = !ADJ && J.tign != nullptr,
                has_tout = !ADJ && J.tout != nullptr, has_tlog = !ADJ && J.tielog != nullptr;
+    const bool counting = stats != nullptr;   // trial and near-tie counters
     double gsum[4] = {0.0, 0.0, 0.0, 0.0};
     unsigned long long n_trials = 0, n_ties = 0;
     int cur = 0;
@@ -648,15 +662,17 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     const int64_t j = jbase + (lr * Wg + lc * 32 + bit);
                     const bool interior = lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC;
                     uint32_t rw0, rw1;
-                    philox_w01((uint32_t)j, (uint32_t)((uint64_t)j >> 32), (uint32_t)t, scen,
-                               k0s, k1s, rw0, rw1);
+                    // counter (cell, 0, step, scenario): a cell index fits 32 bits
+                    // (H, W <= 65 536), so the second word is the constant 0 and
+                    // the first two rounds each need one vector product only
+                    philox_w01((uint32_t)j, 0u, (uint32_t)t, scen, k0s, k1s, rw0, rw1);
                     if (!ign[r]) {  // burning: continue trial
                         if (u24(rw1) < p_cont) {
                             atomicOr(&nR[w], 1u << bit);
                         } else if (interior && has_tout) {
                             gmem(J.tout)[j] = t;
                         }
-                        if (interior) ++n_trials;
+                        if (counting && interior) ++n_trials;
                         continue;
                     }
                     const float qs[8] = {qa[r].x, qa[r].y, qa[r].z, qa[r].w,
@@ -715,8 +731,10 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                         }
                     }
                     if (interior) {
-                        ++n_trials;
-                        if (fabsf(u - P) <= kTieEps) ++n_ties;
+                        if (counting) {
+                            ++n_trials;
+                            if (fabsf(u - P) <= kTieEps) ++n_ties;
+                        }
                         if (!ADJ && has_tlog && fabsf(u - P) <= kTieLogEps) {
                             const unsigned long long n = atomicAdd(J.tie_n, 1ull);
                             if (n < (unsigned long long)kTieLogCap) {
