@@ -269,7 +269,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // then settles on the occupancy it can reach (its warning is silenced).
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Wpass-failed"
-template <int TR, int TC, int KM, bool ADJ, int NT>
+template <int TR, int TC, int KM, bool ADJ, int NT, bool LISTED>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 1 : 5)))
 k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, int32_t ntiles,
        int32_t parity, int32_t t_off, int32_t ksteps, int32_t skip,
@@ -306,9 +306,11 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     const int tid = threadIdx.x;
 
     // ---- work items: every tile (one per work-group), or the tiles the
-    // previous launch marked (worklist: a fixed grid walks the set bits)
+    // previous launch marked (worklist: a fixed grid walks the set bits).
+    // The two are compiled separately, so that launches over every tile carry
+    // none of the worklist's registers.
     __shared__ int sItems, sTile;
-    const bool listed = sched.in != nullptr;
+    constexpr bool listed = LISTED;
     const FS_GLOBAL unsigned long long* sin = gmem(sched.in);
     int my_pre = 0, my_cnt = 0, my_w0 = 0, my_w1 = 0;
     if (listed) {
@@ -1917,13 +1919,16 @@ using StepFn = void (*)(const DevScen*, const int32_t*, int32_t, int32_t, int32_
 struct StepEntry {
     int tr, tc, km, nt;
     bool adj;
-    StepFn fn;
-    int resident;   // work-groups resident at once on the device (0: not queried yet)
+    StepFn fn;        // every tile (skip modes 0 and 2)
+    StepFn fn_list;   // the tiles of a worklist (skip mode 1)
+    int resident;     // work-groups of fn_list resident at once (0: not queried yet)
 };
 
-#define FS_SHAPE_NT(TR, TC, KM, NT)                           \
-    {TR, TC, KM, NT, false, &k_step<TR, TC, KM, false, NT>, 0}, \
-    {TR, TC, KM, NT, true, &k_step<TR, TC, KM, true, NT>, 0},
+#define FS_SHAPE_NT(TR, TC, KM, NT)                                                      \
+    {TR, TC, KM, NT, false, &k_step<TR, TC, KM, false, NT, false>,                         \
+     &k_step<TR, TC, KM, false, NT, true>, 0},                                             \
+    {TR, TC, KM, NT, true, &k_step<TR, TC, KM, true, NT, false>,                           \
+     &k_step<TR, TC, KM, true, NT, true>, 0},
 // 32-row tiles come with both sizes (the default first): 512 lanes shorten
 // the per-step latency of a few busy tiles, 256 lanes give more resident
 // work-groups when many tiles are busy at once (large ensembles).
@@ -1986,7 +1991,7 @@ hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_
         // capped by the caller and by the tile count
         if (e->resident == 0) {
             int per_cu = 0, dev = 0, cus = 0;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->fn, e->nt, 0) !=
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, e->fn_list, e->nt, 0) !=
                     hipSuccess || per_cu < 1)
                 per_cu = 4;
             if (hipGetDevice(&dev) != hipSuccess ||
@@ -1997,8 +2002,9 @@ hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_
         }
         nb = std::max(1, std::min(std::min(grid, e->resident), ntiles));
     }
-    hipLaunchKernelGGL(e->fn, dim3(nb), dim3(e->nt), 0, st, d_jobs, d_tile_job, ntiles,
-                       parity, t_off, ksteps, sched.in ? 0 : skip, lam, rings, sched, d_stats);
+    hipLaunchKernelGGL(sched.in ? e->fn_list : e->fn, dim3(nb), dim3(e->nt), 0, st, d_jobs,
+                       d_tile_job, ntiles, parity, t_off, ksteps, sched.in ? 0 : skip, lam,
+                       rings, sched, d_stats);
     return hipGetLastError();
 }
 
