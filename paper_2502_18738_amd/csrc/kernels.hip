@@ -301,6 +301,10 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     __shared__ uint4 sN[SN ? NW : 1][2];
     __shared__ int sWave[2 * NWAVE];
     __shared__ int sFlag;
+    // all-tile launches find most regions without fire; a worklist's tiles
+    // nearly always hold some, so they skip the test
+    constexpr bool QUIET = !LISTED;
+    __shared__ int sAny[QUIET ? NWAVE : 1];   // per wavefront: a loaded word holds a burning cell
     __shared__ double sG[ADJ ? NWAVE * 4 : 1];
 
     const int tid = threadIdx.x;
@@ -421,10 +425,18 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         }
     }
     if (tid == 0) sFlag = 0;
+    bool myb = false;
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
         dreg[i] = origD[i];
         bprev[i] = origB[i];
+        myb |= origB[i] != 0u;
+    }
+    // read after the first step's opening barrier
+    bool quiet = false;
+    if constexpr (QUIET) {
+        const bool wave_b = __ballot(myb) != 0ull;
+        if ((tid & 63) == 0) sAny[tid >> 6] = wave_b ? 1 : 0;
     }
 
     const uint32_t k0s = J.seed_lo, k1s = J.seed_hi, scen = J.scen_id;
@@ -445,6 +457,18 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
 
     for (int s = 1; s <= kj; ++s) {
         __syncthreads();
+        if (QUIET && s == 1) {
+            // no burning cell in the region: no trial in any step of this
+            // launch (fire moves one cell per step and the halo is KM >= kj
+            // deep), so the tile keeps its state
+            int a = 0;
+#pragma unroll
+            for (int v = 0; v < NWAVE; ++v) a |= sAny[v];
+            if (__builtin_amdgcn_readfirstlane(a) == 0) {
+                quiet = true;
+                break;
+            }
+        }
         const int t = t_base + t_off + s;
         // cells still needed: rows and halo-word bits within kj - s cells of
         // the tile (they are also the ones whose inputs are still valid; trials
@@ -758,6 +782,32 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         cur ^= 1;
     }
     __syncthreads();
+
+    if (QUIET && quiet) {
+        // as a skipped tile: the other buffer is brought up to date once
+        if (!(fin[lt] & 2)) {
+#pragma unroll
+            for (int i = 0; i < WPT; ++i) {
+                const int w = tid + i * NT;
+                if (w < NW) {
+                    const int lr = w / RC, lc = w - (w / RC) * RC;
+                    if (lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC) {
+                        const int gr = r0 + lr, gw = w0 + lc;
+                        if (gr < H && gw < pitch) {
+                            const int64_t o = (int64_t)gr * pitch + gw;
+                            pout[o] = origB[i];
+                            pout[PW + o] = origD[i];
+                        }
+                    }
+                }
+            }
+        }
+        if (tid == 0) {
+            fout[lt] = 2;
+            if (stats) atomicAdd(&stats[0], 1ull);
+        }
+        continue;
+    }
 
     // ---- write the tile interior back
     bool anyB = false, changed = false;
