@@ -287,7 +287,15 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     // successful trials of step t, which are exactly the burning cells of S(t).
     // The burned plane of a word lives in its owner thread's registers.
     __shared__ uint32_t sB[2][NW];
-    __shared__ uint16_t sL[LCAP];
+    // The list holds LCH entries.  A step with more trials places and takes
+    // them in chunks of LCH (a barrier between chunks).  256-lane shapes keep
+    // 8 entries per lane, so that their LDS does not limit how many
+    // work-groups share a compute unit; 512-lane shapes (one busy work-group
+    // per compute unit) and one-step shapes (small regions, whose occupancy
+    // the chunk loop's registers would lower) keep the worst case.
+    constexpr int LCH = (NT >= 512 || KM == 1 || LCAP < 8 * NT) ? LCAP : 8 * NT;
+    constexpr bool CHUNKED = LCH < LCAP;
+    __shared__ uint16_t sL[LCH];
     // words holding a trial this step, one segment per wavefront (its lanes'
     // words in lane order): (word index, trial mask, ignition mask, offset of
     // the word's first list entry within the wavefront's trials)
@@ -595,6 +603,8 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             break;
         }
 
+        for (int c0 = 0;; c0 += LCH) {
+        const int cend = CHUNKED ? min(ntr, c0 + LCH) : ntr;
         for (int x = tid; x < tot_w * 8; x += NT) {
             // lane x & 7 of listed word k = x >> 3 places the trials among its
             // bits 4 (x & 7) .. 4 (x & 7) + 3; the word sits in the segment of
@@ -612,12 +622,13 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             const uint4 wl = sWL[seg * SEG + (k - kb)];
             const int b0 = (x & 7) * 4;
             const uint32_t m = (wl.y >> b0) & 15u;
-            int pos = tb + (int)wl.w + __popc(wl.y & ((1u << b0) - 1u));
+            int pos = tb + (int)wl.w + __popc(wl.y & ((1u << b0) - 1u)) - c0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 if ((m >> q) & 1u) {
                     const int b = b0 + q;
-                    sL[pos] = (uint16_t)((wl.x * 32 + b) | (((wl.z >> b) & 1u) ? 0x8000u : 0u));
+                    if (!CHUNKED || (unsigned)pos < (unsigned)LCH)
+                        sL[pos] = (uint16_t)((wl.x * 32 + b) | (((wl.z >> b) & 1u) ? 0x8000u : 0u));
                     ++pos;
                 }
             }
@@ -641,7 +652,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             // flat index of the region's top-left cell (may be negative; every
             // listed cell lies inside the grid)
             const int64_t jbase = (int64_t)r0 * Wg + (int64_t)w0 * 32;
-            for (int k0 = 0; k0 < ntr; k0 += R * NT) {
+            for (int k0 = c0; k0 < cend; k0 += R * NT) {
                 int ent[R], ign[R];
                 fs_f4 qa[R], qb[R];
                 fs_f4 ta[R], tb[R];   // adjoint only
@@ -649,9 +660,9 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 float lj[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    if (k0 + r * NT >= ntr) break;   // uniform: no lane has trial r
+                    if (k0 + r * NT >= cend) break;   // uniform: no lane has trial r
                     const int k = k0 + r * NT + tid;
-                    ent[r] = k < ntr ? (int)sL[k] : 0;
+                    ent[r] = k < cend ? (int)sL[k - c0] : 0;
                     ign[r] = (ent[r] >> 15) & 1;
                     ent[r] &= 0x7FFF;
                     qa[r] = qb[r] = (fs_f4)(0.f);
@@ -660,7 +671,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                         rc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
                         lj[r] = 0.f;
                     }
-                    if (k < ntr && ign[r]) {
+                    if (k < cend && ign[r]) {
                         const int w = ent[r] >> 5, bit = ent[r] & 31;
                         const int lr = w / RC, lc = w - (w / RC) * RC;
                         const int64_t j = jbase + (lr * Wg + lc * 32 + bit);
@@ -680,9 +691,9 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 }
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    if (k0 + r * NT >= ntr) break;
+                    if (k0 + r * NT >= cend) break;
                     const int k = k0 + r * NT + tid;
-                    if (k >= ntr) continue;
+                    if (k >= cend) continue;
                     const int w = ent[r] >> 5, bit = ent[r] & 31;
                     const int lr = w / RC, lc = w - (w / RC) * RC;
                     const int64_t j = jbase + (lr * Wg + lc * 32 + bit);
@@ -778,6 +789,18 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                 }
             }
         }
+        if (!CHUNKED || c0 + LCH >= ntr) break;   // uniform
+        __syncthreads();   // the chunk's entries are taken
+        // the prefixes again (read here so that they are not held through
+        // the trials)
+        acc = 0;
+#pragma unroll
+        for (int v = 0; v < NWAVE; ++v) {
+            tp[v] = acc & 0xFFFF;
+            bp[v] = acc >> 16;
+            acc += sWave[v];
+        }
+        }  // chunks
         // the next step's opening barrier completes this step's trials
         cur ^= 1;
     }

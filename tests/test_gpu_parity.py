@@ -170,6 +170,42 @@ def test_execution_shapes_are_bit_identical(Sim):
             assert np.array_equal(acc, ref[1]), ex
 
 
+# 256-lane shapes whose trial list (8 entries per lane) is shorter than their
+# region: a step with more trials places and takes them in chunks
+CHUNK_SHAPES = [
+    dict(tile_rows=32, tile_words=4, depth=8, skip=2, threads=256),
+    dict(tile_rows=16, tile_words=8, depth=8, skip=0),
+    dict(tile_rows=16, tile_words=4, depth=4, skip=1),
+    dict(tile_rows=32, tile_words=2, depth=32, skip=1, threads=256),
+]
+
+
+@pytest.mark.parametrize("ex", CHUNK_SHAPES, ids=lambda e: "%dx%dd%ds%d" % (
+    e["tile_rows"], e["tile_words"], e["depth"], int(e["skip"])))
+def test_dense_fire_takes_the_trial_list_in_chunks(Sim, ex):
+    """A burning block: nearly every cell of the busy tiles' regions has a
+    trial, several times what the list holds.  One step at a time from the
+    oracle's states (bit-exact outside near ties), then a blocked run of all
+    steps (outside the ties' light cones)."""
+    H, W, T = 192, 320, 6
+    s = synth.make_lakes(H, W, 21, T=T)
+    S0 = np.zeros((H, W), np.uint8)
+    S0[12:180, 16:304] = 1
+    S0[s.p_veg <= -1.0] = 0   # lake cells stay unburnable
+    states, ties = oracle_traj(s, T, S0=S0)
+    say("dense fire", ex, "burning:", int((S0 == 1).sum()))
+    sim = Sim([s], exec=ex)
+    for t in range(1, T + 1):
+        sim.set_state(0, synth.encode_planes(states[t - 1]), t - 1)
+        sim.run(1)
+        g = gstate(sim)
+        bad = g != states[t]
+        assert not np.any(bad & ~ties[t]), (t, np.argwhere(bad & ~ties[t])[:5])
+    sim.set_state(0, synth.encode_planes(S0), 0)
+    sim.run(T)
+    check_light_cone(gstate(sim), states, ties, T)
+
+
 def test_blocked_run_equals_oracle_final_state(Sim):
     """A temporally blocked, tile-skipping run reaches the oracle's final state
     (up to near-tie flips inside their light cones)."""
