@@ -82,6 +82,7 @@ __device__ __forceinline__ FS_GLOBAL T* gmem(T* p) {
 // 16-byte vector read through a global pointer (HIP's float4 cannot be copied
 // out of a non-generic address space).
 typedef float fs_f4 __attribute__((ext_vector_type(4)));
+typedef int fs_i4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ float4 load_f4(const void* base, int64_t i) {
     const fs_f4 v = ((const FS_GLOBAL fs_f4*)base)[i];
     return make_float4(v.x, v.y, v.z, v.w);
@@ -1318,31 +1319,46 @@ k_init_state(const DevScen* __restrict__ jobs, const int32_t* __restrict__ ib0, 
 // Calibration maps at a reset, one thread per cell: accumulator 1 on the
 // initial burning cells (a constant) and 0 elsewhere, ignition step 0 or
 // never, burn-out step never.
+// One grid row per scenario (blockIdx.y).  A thread writes 4 consecutive
+// cells with 16-byte stores (the maps of a scenario start 256-byte aligned);
+// block 0 writes the last cells of a grid whose size is not a multiple of 4.
 __global__ void __launch_bounds__(256)
-k_init_maps(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0, int32_t n,
-            int64_t nvb) {
-    int lo = 0;
-    {
-        const int64_t g0 = (int64_t)blockIdx.x * 256;
-        int hi = n;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (cell0[mid] <= g0) lo = mid; else hi = mid;
+k_init_maps(const DevScen* __restrict__ jobs) {
+    const DevScen& J = jobs[blockIdx.y];
+    const int W = J.W, pitch = J.pitch;
+    const int64_t cells = (int64_t)J.H * W, nq = cells >> 2;
+    const FS_GLOBAL uint32_t* init = gmem(J.init);
+    auto burning = [&](int r, int c) -> bool {
+        return (init[(int64_t)r * pitch + (c >> 5)] >> (c & 31)) & 1u;
+    };
+    FS_GLOBAL fs_f4* yh = gmem(reinterpret_cast<fs_f4*>(J.yhat));
+    FS_GLOBAL fs_i4* tg = gmem(reinterpret_cast<fs_i4*>(J.tign));
+    FS_GLOBAL fs_i4* to = gmem(reinterpret_cast<fs_i4*>(J.tout));
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nq;
+         q += (int64_t)gridDim.x * 256) {
+        int r = (int)((4 * q) / W), c = (int)(4 * q - (int64_t)r * W);
+        float y[4];
+        int t[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bool b = burning(r, c);
+            y[e] = b ? 1.f : 0.f;
+            t[e] = b ? 0 : INT_MAX;
+            if (++c == W) {
+                c = 0;
+                ++r;
+            }
         }
+        yh[q] = fs_f4{y[0], y[1], y[2], y[3]};
+        tg[q] = fs_i4{t[0], t[1], t[2], t[3]};
+        to[q] = fs_i4{INT_MAX, INT_MAX, INT_MAX, INT_MAX};
     }
-    for (int64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        const int64_t g0 = vb * 256;
-        while (lo < n - 1 && g0 >= cell0[lo + 1]) ++lo;
-        const int64_t gi = g0 + threadIdx.x;
-        if (gi >= cell0[n]) continue;
-        int s = lo;
-        while (gi >= cell0[s + 1]) ++s;
-        const DevScen& J = jobs[s];
-        const int64_t j = gi - cell0[s];
-        const int r = (int)(j / J.W), c = (int)(j - (int64_t)r * J.W);
-        const bool burning = (gmem(J.init)[(int64_t)r * J.pitch + (c >> 5)] >> (c & 31)) & 1u;
-        gmem(J.yhat)[j] = burning ? 1.f : 0.f;
-        gmem(J.tign)[j] = burning ? 0 : INT_MAX;
+    if (blockIdx.x == 0 && threadIdx.x < (int)(cells & 3)) {
+        const int64_t j = 4 * nq + threadIdx.x;
+        const int r = (int)(j / W), c = (int)(j - (int64_t)r * W);
+        const bool b = burning(r, c);
+        gmem(J.yhat)[j] = b ? 1.f : 0.f;
+        gmem(J.tign)[j] = b ? 0 : INT_MAX;
         gmem(J.tout)[j] = INT_MAX;
     }
 }
@@ -1534,25 +1550,45 @@ k_grad_reduce(const double* __restrict__ gpart, const int32_t* __restrict__ rang
 // scenario.
 
 // Bounding box of (yhat != 0) | (y != 0): box = {rmin, rmax, cmin, cmax}.  A
-// block strides over rows, reduces its own box in LDS and merges it with four
-// atomics, so the atomics do not contend per cell.
+// block strides over its scenario, reduces its own box in LDS and merges it
+// with four atomics, so the atomics do not contend per cell.  Rows of a
+// multiple of 4 cells with a 4-byte aligned target are read 4 cells at a time
+// (16-byte yhat, 4-byte target loads), other grids cell by cell.
 __global__ void __launch_bounds__(256)
 k_loss_box(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0,
            const uint8_t* __restrict__ y_all, int* __restrict__ box_all) {
     const DevScen& J = jobs[blockIdx.y];
     const float* yhat = J.yhat;
     const uint8_t* y = y_all + cell0[blockIdx.y];
+    const int W = J.W;
     int v[4] = {INT_MAX, -1, INT_MAX, -1};
-    for (int r = blockIdx.x; r < J.H; r += gridDim.x)
-        for (int c = threadIdx.x; c < J.W; c += 256) {
-            const int64_t j = (int64_t)r * J.W + c;
-            if (yhat[j] != 0.f || y[j] != 0) {
-                v[0] = min(v[0], r);
-                v[1] = max(v[1], r);
-                v[2] = min(v[2], c);
-                v[3] = max(v[3], c);
-            }
+    auto hit = [&](int r, int c) {
+        v[0] = min(v[0], r);
+        v[1] = max(v[1], r);
+        v[2] = min(v[2], c);
+        v[3] = max(v[3], c);
+    };
+    if ((W & 3) == 0 && ((uintptr_t)y & 3u) == 0) {
+        const int64_t nq = (int64_t)J.H * W / 4;
+        const FS_GLOBAL fs_f4* y4 = gmem(reinterpret_cast<const fs_f4*>(yhat));
+        const FS_GLOBAL uint32_t* t4 = gmem(reinterpret_cast<const uint32_t*>(y));
+        for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nq;
+             q += (int64_t)gridDim.x * 256) {
+            const fs_f4 a = y4[q];
+            const uint32_t b = t4[q];
+            const int r = (int)((4 * q) / W), c = (int)(4 * q - (int64_t)r * W);
+            if (a.x != 0.f || (b & 0xFFu)) hit(r, c);
+            if (a.y != 0.f || (b & 0xFF00u)) hit(r, c + 1);
+            if (a.z != 0.f || (b & 0xFF0000u)) hit(r, c + 2);
+            if (a.w != 0.f || (b & 0xFF000000u)) hit(r, c + 3);
         }
+    } else {
+        for (int r = blockIdx.x; r < J.H; r += gridDim.x)
+            for (int c = threadIdx.x; c < W; c += 256) {
+                const int64_t j = (int64_t)r * W + c;
+                if (yhat[j] != 0.f || y[j] != 0) hit(r, c);
+            }
+    }
     __shared__ int sh[4][256];
     for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] = v[m];
     __syncthreads();
@@ -1597,23 +1633,46 @@ k_loss_terms(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0
     const int Hp = H / 4, Wp = W / 4;
     const double Np = (double)Hp * (double)Wp;
     double bce = 0.0, mse = 0.0;
-    for (int r = 4 * pr; r < min(H, 4 * pr + 4); ++r)
-        for (int c = threadIdx.x; c < W; c += 256) {
-            const int64_t j = (int64_t)r * W + c;
-            double lam = 0.0;
-            if ((kind == 0 || kind == 1) && has_box && r >= b0 && r <= b1 && c >= c0 && c <= c1) {
-                // BCE with logits per cell in FP32, -(y log s + (1 - y) log(1 - s))
-                // with s = sigmoid(z), written as softplus(z) - y z; its derivative
-                // is s - y.  The sums over cells are FP64.
-                const float z = yhat[j], yy = (float)y[j];
-                const float e = expf(-fabsf(z));
-                const float sp = fmaxf(z, 0.f) + log1pf(e);
-                const float sig = z >= 0.f ? 1.f / (1.f + e) : e / (1.f + e);
-                bce += (double)(sp - yy * z);
-                lam += (double)(sig - yy) * invN;
-            }
-            lambda[j] = (float)lam;
+    const bool use_bce = (kind == 0 || kind == 1) && has_box;
+    // BCE with logits per cell in FP32, -(y log s + (1 - y) log(1 - s)) with
+    // s = sigmoid(z), written as softplus(z) - y z; its derivative is s - y.
+    // The sums over cells are FP64.  Returns the cell's lambda.
+    auto cell = [&](int r, int c, float z, float yy) -> float {
+        double lam = 0.0;
+        if (use_bce && r >= b0 && r <= b1 && c >= c0 && c <= c1) {
+            const float e = expf(-fabsf(z));
+            const float sp = fmaxf(z, 0.f) + log1pf(e);
+            const float sig = z >= 0.f ? 1.f / (1.f + e) : e / (1.f + e);
+            bce += (double)(sp - yy * z);
+            lam += (double)(sig - yy) * invN;
         }
+        return (float)lam;
+    };
+    const int r_end = min(H, 4 * pr + 4);
+    if ((W & 3) == 0 && ((uintptr_t)y & 3u) == 0 && ((uintptr_t)lambda & 15u) == 0) {
+        // 4 cells per thread: 16-byte yhat and lambda, 4-byte target accesses
+        const int64_t q0 = (int64_t)pr * W, q1 = (int64_t)r_end * W / 4;
+        const FS_GLOBAL fs_f4* y4 = gmem(reinterpret_cast<const fs_f4*>(yhat));
+        const FS_GLOBAL uint32_t* t4 = gmem(reinterpret_cast<const uint32_t*>(y));
+        FS_GLOBAL fs_f4* l4 = gmem(reinterpret_cast<fs_f4*>(lambda));
+        for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
+            const fs_f4 a = y4[q];
+            const uint32_t b = t4[q];
+            const int r = (int)((4 * q) / W), c = (int)(4 * q - (int64_t)r * W);
+            fs_f4 o;
+            o.x = cell(r, c, a.x, (float)(b & 0xFFu));
+            o.y = cell(r, c + 1, a.y, (float)((b >> 8) & 0xFFu));
+            o.z = cell(r, c + 2, a.z, (float)((b >> 16) & 0xFFu));
+            o.w = cell(r, c + 3, a.w, (float)(b >> 24));
+            l4[q] = o;
+        }
+    } else {
+        for (int r = 4 * pr; r < r_end; ++r)
+            for (int c = threadIdx.x; c < W; c += 256) {
+                const int64_t j = (int64_t)r * W + c;
+                lambda[j] = cell(r, c, yhat[j], (float)y[j]);
+            }
+    }
     __syncthreads();
     if ((kind == 1 || kind == 2) && pr < Hp) {
         for (int pc = threadIdx.x; pc < Wp; pc += 256) {
@@ -1886,10 +1945,11 @@ hipError_t launch_init_state(hipStream_t st, const DevScen* d_jobs, const int32_
     if (nblocks > 0)
         hipLaunchKernelGGL(k_init_state, dim3(std::min(nblocks, 16384)), dim3(256), 0, st,
                            d_jobs, d_ib0, n, nblocks);
-    if (maps && total_cells > 0) {
-        const int64_t nvb = (total_cells + 255) / 256;
-        hipLaunchKernelGGL(k_init_maps, dim3((unsigned)std::min<int64_t>(nvb, 16384)), dim3(256),
-                           0, st, d_jobs, d_cell0, n, nvb);
+    if (maps && total_cells > 0 && n > 0) {
+        // 4 cells per thread; a grid row per scenario, strided over its cells
+        const int64_t per = (total_cells / n + 1023) / 1024;
+        hipLaunchKernelGGL(k_init_maps, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(per, 512)),
+                                             (unsigned)n), dim3(256), 0, st, d_jobs);
     }
     return hipGetLastError();
 }
@@ -1969,7 +2029,7 @@ hipError_t launch_loss(hipStream_t st, const DevScen* d_jobs, const int64_t* d_c
     if (n <= 0) return hipSuccess;
     const int maxparts = (max_h + 3) / 4;
     hipLaunchKernelGGL(k_box_init, dim3(1), dim3(256), 0, st, d_jobs, n, d_box);
-    hipLaunchKernelGGL(k_loss_box, dim3(64, n), dim3(256), 0, st, d_jobs, d_cell0, y, d_box);
+    hipLaunchKernelGGL(k_loss_box, dim3(128, n), dim3(256), 0, st, d_jobs, d_cell0, y, d_box);
     hipLaunchKernelGGL(k_loss_terms, dim3(maxparts, n), dim3(256), 0, st, d_jobs, d_cell0, y,
                        kind, d_box, lambda, d_part, maxparts);
     hipLaunchKernelGGL(k_loss_final, dim3(n), dim3(256), 0, st, d_jobs, kind, d_box, d_part,
