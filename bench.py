@@ -137,9 +137,12 @@ def timed(fn, steps, warmup, torch):
 
 
 def step_kernel_name(ex):
-    return "k_step<{},{},{},false,{}>".format(
+    """The forward step instantiation of an execution shape (the last template
+    argument: worklist launches, skip mode 1)."""
+    return "k_step<{},{},{},false,{},{}>".format(
         ex["tile_rows"], ex["tile_words"], km_bucket(ex["depth"]),
-        ex.get("threads") or (512 if ex["tile_rows"] >= 32 else 256))
+        ex.get("threads") or (512 if ex["tile_rows"] >= 32 else 256),
+        "true" if int(ex["skip"]) == 1 else "false")
 
 
 def work_counts(Sim, scs, ex, T, torch):

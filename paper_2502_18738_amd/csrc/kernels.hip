@@ -1334,9 +1334,20 @@ k_init_maps(const DevScen* __restrict__ jobs) {
     FS_GLOBAL fs_f4* yh = gmem(reinterpret_cast<fs_f4*>(J.yhat));
     FS_GLOBAL fs_i4* tg = gmem(reinterpret_cast<fs_i4*>(J.tign));
     FS_GLOBAL fs_i4* to = gmem(reinterpret_cast<fs_i4*>(J.tout));
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nq;
-         q += (int64_t)gridDim.x * 256) {
-        int r = (int)((4 * q) / W), c = (int)(4 * q - (int64_t)r * W);
+    // (row, column) of the quad's first cell, advanced by the stride without
+    // a division per quad
+    const int64_t q_first = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t step = 4 * (int64_t)gridDim.x * 256;
+    const int dR = (int)(step / W), dC = (int)(step - (int64_t)dR * W);
+    int qr = (int)((4 * q_first) / W), qc = (int)(4 * q_first - (int64_t)qr * W);
+    for (int64_t q = q_first; q < nq; q += step / 4) {
+        int r = qr, c = qc;
+        qc += dC;
+        qr += dR;
+        if (qc >= W) {
+            qc -= W;
+            ++qr;
+        }
         float y[4];
         int t[4];
 #pragma unroll
@@ -1572,15 +1583,23 @@ k_loss_box(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0,
         const int64_t nq = (int64_t)J.H * W / 4;
         const FS_GLOBAL fs_f4* y4 = gmem(reinterpret_cast<const fs_f4*>(yhat));
         const FS_GLOBAL uint32_t* t4 = gmem(reinterpret_cast<const uint32_t*>(y));
-        for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nq;
-             q += (int64_t)gridDim.x * 256) {
+        const int64_t q_first = (int64_t)blockIdx.x * 256 + threadIdx.x;
+        const int64_t step = 4 * (int64_t)gridDim.x * 256;
+        const int dR = (int)(step / W), dC = (int)(step - (int64_t)dR * W);
+        int r = (int)((4 * q_first) / W), c = (int)(4 * q_first - (int64_t)r * W);
+        for (int64_t q = q_first; q < nq; q += step / 4) {
             const fs_f4 a = y4[q];
             const uint32_t b = t4[q];
-            const int r = (int)((4 * q) / W), c = (int)(4 * q - (int64_t)r * W);
             if (a.x != 0.f || (b & 0xFFu)) hit(r, c);
             if (a.y != 0.f || (b & 0xFF00u)) hit(r, c + 1);
             if (a.z != 0.f || (b & 0xFF0000u)) hit(r, c + 2);
             if (a.w != 0.f || (b & 0xFF000000u)) hit(r, c + 3);
+            c += dC;   // the next quad of this thread (a row holds a multiple of 4 cells)
+            r += dR;
+            if (c >= W) {
+                c -= W;
+                ++r;
+            }
         }
     } else {
         for (int r = blockIdx.x; r < J.H; r += gridDim.x)
@@ -1655,16 +1674,23 @@ k_loss_terms(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0
         const FS_GLOBAL fs_f4* y4 = gmem(reinterpret_cast<const fs_f4*>(yhat));
         const FS_GLOBAL uint32_t* t4 = gmem(reinterpret_cast<const uint32_t*>(y));
         FS_GLOBAL fs_f4* l4 = gmem(reinterpret_cast<fs_f4*>(lambda));
+        const int dR = 1024 / W, dC = 1024 - dR * W;   // 256 quads on
+        int r = 4 * pr + (4 * (int)threadIdx.x) / W, c = (4 * (int)threadIdx.x) % W;
         for (int64_t q = q0 + threadIdx.x; q < q1; q += 256) {
             const fs_f4 a = y4[q];
             const uint32_t b = t4[q];
-            const int r = (int)((4 * q) / W), c = (int)(4 * q - (int64_t)r * W);
             fs_f4 o;
             o.x = cell(r, c, a.x, (float)(b & 0xFFu));
             o.y = cell(r, c + 1, a.y, (float)((b >> 8) & 0xFFu));
             o.z = cell(r, c + 2, a.z, (float)((b >> 16) & 0xFFu));
             o.w = cell(r, c + 3, a.w, (float)(b >> 24));
             l4[q] = o;
+            c += dC;
+            r += dR;
+            if (c >= W) {
+                c -= W;
+                ++r;
+            }
         }
     } else {
         for (int r = 4 * pr; r < r_end; ++r)
