@@ -264,14 +264,24 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // --------------------------------------------------------------- main step
 
 // 256-lane shapes serve many busy tiles at once (ensembles, calibration): they
-// aim at 96 registers so that 5 wavefronts share a SIMD, and they keep no
-// per-word slot masks in LDS (see SN below), so that more work-groups fit a CU.
-// Shapes with several words per lane cannot reach that target; the compiler
-// then settles on the occupancy it can reach (its warning is silenced).
+// keep no per-word slot masks in LDS (see SN below), so that more work-groups
+// fit a CU, and they aim at a register budget per wavefront: 64 registers (8
+// wavefronts per SIMD) for launches over every tile with up to 2 words per
+// lane, 72 (7) for those with more, 96 (5) for worklist and adjoint launches,
+// whose longer-lived state would spill below that (measured: the tighter
+// targets gain 2-4 % on calibration and the ensemble).  Where a shape cannot
+// reach its target the compiler settles on the occupancy it can reach (its
+// warning is silenced).
+template <int TR, int TC, int KM, bool ADJ, int NT, bool LISTED>
+constexpr int step_waves() {
+    constexpr int wpt = ((TR + 2 * KM) * (TC + 2) + NT - 1) / NT;
+    return NT >= 512 ? 1 : (ADJ || LISTED) ? 5 : (wpt <= 2 ? 8 : 7);
+}
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Wpass-failed"
 template <int TR, int TC, int KM, bool ADJ, int NT, bool LISTED>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT >= 512 ? 1 : 5)))
+__global__ void __launch_bounds__(NT)
+    __attribute__((amdgpu_waves_per_eu(step_waves<TR, TC, KM, ADJ, NT, LISTED>())))
 k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, int32_t ntiles,
        int32_t parity, int32_t t_off, int32_t ksteps, int32_t skip,
        const float* __restrict__ lam, Rings rings, Sched sched,
