@@ -31,6 +31,7 @@ namespace {
 
 constexpr float kRad2Deg = 57.295779513082320876798f;
 constexpr float kSqrtHalf = 0.70710678118654752440f;
+constexpr float kLog2e = 1.44269504088896340736f;
 constexpr float kTwoM24 = 5.9604644775390625e-08f;  // 2^-24
 constexpr float kTieEps = 1e-5f;
 
@@ -111,6 +112,24 @@ struct Edge {
     float q, ez, x, th, vterm;
 };
 
+// e^z as 2^(z log2 e) on the hardware exponential: relative error about
+// |z| 2^-24 (the rounding of the product) plus one ulp, at a quarter of the
+// library expf's instructions.  The per-edge tables and the adjoints use it
+// alike, so the adjoints see the bits the tables were built from.
+__device__ __forceinline__ float exp_hw(float z) { return __builtin_amdgcn_exp2f(z * kLog2e); }
+
+// tanh, branch-free and odd: the Taylor series to y^9 below |y| = 0.25
+// (truncation below 1e-8 relative), else 1 - 2 / (e^(2|y|) + 1) with the
+// hardware reciprocal (relative error below 1e-6 there, where tanh > 0.24).
+__device__ __forceinline__ float tanh_fast(float y) {
+    const float a = fabsf(y), s = a * a;
+    const float p = a * fmaf(s, fmaf(s, fmaf(s, fmaf(s, 62.f / 2835.f, -17.f / 315.f),
+                                                2.f / 15.f), -1.f / 3.f), 1.f);
+    const float e = exp_hw(2.f * a);
+    const float r = fmaf(-2.f, __builtin_amdgcn_rcpf(e + 1.f), 1.f);
+    return copysignf(a < 0.25f ? p : r, y);
+}
+
 __device__ __forceinline__ Edge edge_terms(const DevScen& J, float4 rec, float th, int dr,
                                            int dc) {
     const bool diag = (dr != 0) && (dc != 0);
@@ -120,9 +139,9 @@ __device__ __forceinline__ Edge edge_terms(const DevScen& J, float4 rec, float t
     if (diag) proj = proj * kSqrtHalf;
     e.vterm = proj - rec.y;                               // V (cos(delta) - 1)
     const float z = J.c1 * rec.y + J.c2 * e.vterm + J.a * e.th;   // Eq. 3, 4 exponents
-    e.ez = expf(z);
+    e.ez = exp_hw(z);
     e.x = (J.p_h * rec.x) * e.ez;                         // Eq. 2
-    e.q = tanhf(J.c * e.x);                               // Eq. 5
+    e.q = tanh_fast(J.c * e.x);                           // Eq. 5
     return e;
 }
 
@@ -222,7 +241,7 @@ __device__ __forceinline__ void pignite_grad_tab(const EdgeParams& J, float4 rec
         const float vterm = proj - rec.y;
         // F e^z with the operations of edge_terms, so it has the bits the
         // table pass used for q
-        const float gv = rec.x * expf(J.c1 * rec.y + J.c2 * vterm + J.a * th[m]);
+        const float gv = rec.x * exp_hw(J.c1 * rec.y + J.c2 * vterm + J.a * th[m]);
         const float x = J.p_h * gv;
         const float sc = pre[m] * suf[m] * (J.c * (1.f - q[m] * q[m]));
         gl[0] = gl[0] + sc * gv;
@@ -1066,10 +1085,11 @@ k_qtable(const DevScen* __restrict__ jobs, const int4* __restrict__ qbox,
         o[1] = fs_f4{q[4], q[5], q[6], q[7]};
     };
     // region index i of scenario s -> grid cell
+    // (a region holds at most 65 536^2 cells, so i fits 32 unsigned bits)
     auto at = [&](int s, int64_t i) {
         const int4 q = qbox[s];
-        const int rr = (int)(i / q.z);
-        return (int64_t)(q.x + rr) * jobs[s].W + (q.y + (int)(i - (int64_t)rr * q.z));
+        const uint32_t ii = (uint32_t)i, rr = ii / (uint32_t)q.z;
+        return (int64_t)(q.x + (int)rr) * jobs[s].W + (q.y + (int)(ii - rr * (uint32_t)q.z));
     };
     const int64_t total = cell0[n];
     const int64_t nvb = (total + 255) / 256;
