@@ -1813,30 +1813,49 @@ k_box_init(const DevScen* __restrict__ jobs, int32_t n, int* __restrict__ box_al
 
 // ------------------------------------------------- checkpoints, parameters
 
+// Copy of nw 32-bit words from src to d0 (and d1 unless null) by the
+// blocks of one grid row: 16 bytes per lane where all pointers are 16-byte
+// aligned, the remaining words one by one.
+__device__ __forceinline__ void copy_words(uint32_t* d0, uint32_t* d1, const uint32_t* src,
+                                           int64_t nw) {
+    const int64_t t0 = (int64_t)blockIdx.x * 256 + threadIdx.x, st = (int64_t)gridDim.x * 256;
+    int64_t done = 0;
+    if ((((uintptr_t)d0 | (uintptr_t)d1 | (uintptr_t)src) & 15u) == 0) {
+        const int64_t nq = nw >> 2;
+        const FS_GLOBAL fs_i4* s4 = gmem(reinterpret_cast<const fs_i4*>(src));
+        FS_GLOBAL fs_i4* a4 = gmem(reinterpret_cast<fs_i4*>(d0));
+        FS_GLOBAL fs_i4* b4 = gmem(reinterpret_cast<fs_i4*>(d1));
+        for (int64_t i = t0; i < nq; i += st) {
+            const fs_i4 v = s4[i];
+            a4[i] = v;
+            if (d1) b4[i] = v;
+        }
+        done = nq << 2;
+    }
+    for (int64_t i = done + t0; i < nw; i += st) {
+        const uint32_t v = src[i];
+        d0[i] = v;
+        if (d1) d1[i] = v;
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_ckpt_save(const DevScen* __restrict__ jobs, int32_t parity, int32_t slot) {
     const DevScen& J = jobs[blockIdx.y];
     const int64_t nw = 2 * (int64_t)J.H * J.pitch;
-    const uint32_t* src = J.planes[parity];
-    uint32_t* dst = J.ckpt + (int64_t)slot * nw;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nw; i += (int64_t)gridDim.x * 256)
-        dst[i] = src[i];
+    copy_words(J.ckpt + (int64_t)slot * nw, nullptr, J.planes[parity], nw);
 }
 
 __global__ void __launch_bounds__(256)
 k_ckpt_load(const DevScen* __restrict__ jobs) {
     const DevScen& J = jobs[blockIdx.y];
-    const int64_t nw = 2 * (int64_t)J.H * J.pitch;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nw; i += (int64_t)gridDim.x * 256)
-        J.planes[0][i] = J.planes[1][i] = J.ckpt[i];
+    copy_words(J.planes[0], J.planes[1], J.ckpt, 2 * (int64_t)J.H * J.pitch);
 }
 
 __global__ void __launch_bounds__(256)
 k_dup_planes(const DevScen* __restrict__ jobs, int32_t parity) {
     const DevScen& J = jobs[blockIdx.y];
-    const int64_t nw = 2 * (int64_t)J.H * J.pitch;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nw; i += (int64_t)gridDim.x * 256)
-        J.planes[parity ^ 1][i] = J.planes[parity][i];
+    copy_words(J.planes[parity ^ 1], nullptr, J.planes[parity], 2 * (int64_t)J.H * J.pitch);
 }
 
 // Worklist of the first launch: tiles with a burning cell in their 3 x 3
@@ -1885,14 +1904,14 @@ __global__ void k_set_seeds(DevScen* jobs, SeedBlock sb) {
 hipError_t launch_ckpt_save(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
                             int32_t slot, int64_t max_words) {
     if (n <= 0) return hipSuccess;
-    const unsigned gx = (unsigned)std::min<int64_t>((2 * max_words + 255) / 256, 1024);
+    const unsigned gx = (unsigned)std::min<int64_t>((2 * max_words + 1023) / 1024, 1024);
     hipLaunchKernelGGL(k_ckpt_save, dim3(gx, n), dim3(256), 0, st, d_jobs, parity, slot);
     return hipGetLastError();
 }
 
 hipError_t launch_ckpt_load(hipStream_t st, const DevScen* d_jobs, int32_t n, int64_t max_words) {
     if (n <= 0) return hipSuccess;
-    const unsigned gx = (unsigned)std::min<int64_t>((2 * max_words + 255) / 256, 1024);
+    const unsigned gx = (unsigned)std::min<int64_t>((2 * max_words + 1023) / 1024, 1024);
     hipLaunchKernelGGL(k_ckpt_load, dim3(gx, n), dim3(256), 0, st, d_jobs);
     return hipGetLastError();
 }
