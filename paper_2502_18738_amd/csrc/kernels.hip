@@ -32,6 +32,7 @@ namespace {
 constexpr float kRad2Deg = 57.295779513082320876798f;
 constexpr float kSqrtHalf = 0.70710678118654752440f;
 constexpr float kLog2e = 1.44269504088896340736f;
+constexpr float kLn2 = 0.69314718055994530942f;
 constexpr float kTwoM24 = 5.9604644775390625e-08f;  // 2^-24
 constexpr float kTieEps = 1e-5f;
 
@@ -1620,10 +1621,18 @@ k_loss_box(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0,
         for (int64_t q = q_first; q < nq; q += step / 4) {
             const fs_f4 a = y4[q];
             const uint32_t b = t4[q];
-            if (a.x != 0.f || (b & 0xFFu)) hit(r, c);
-            if (a.y != 0.f || (b & 0xFF00u)) hit(r, c + 1);
-            if (a.z != 0.f || (b & 0xFF0000u)) hit(r, c + 2);
-            if (a.w != 0.f || (b & 0xFF000000u)) hit(r, c + 3);
+            // the quad's cells that count, one bit each: one update of the row
+            // bounds, the columns from the first and last such cell
+            const uint32_t nz = ((a.x != 0.f || (b & 0xFFu)) ? 1u : 0u) |
+                                ((a.y != 0.f || (b & 0xFF00u)) ? 2u : 0u) |
+                                ((a.z != 0.f || (b & 0xFF0000u)) ? 4u : 0u) |
+                                ((a.w != 0.f || (b & 0xFF000000u)) ? 8u : 0u);
+            if (nz) {
+                v[0] = min(v[0], r);
+                v[1] = max(v[1], r);
+                v[2] = min(v[2], c + __builtin_ctz(nz));
+                v[3] = max(v[3], c + 31 - __builtin_clz(nz));
+            }
             c += dC;   // the next quad of this thread (a row holds a multiple of 4 cells)
             r += dR;
             if (c >= W) {
@@ -1685,13 +1694,17 @@ k_loss_terms(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0
     const bool use_bce = (kind == 0 || kind == 1) && has_box;
     // BCE with logits per cell in FP32, -(y log s + (1 - y) log(1 - s)) with
     // s = sigmoid(z), written as softplus(z) - y z; its derivative is s - y.
-    // The sums over cells are FP64.  Returns the cell's lambda.
+    // e = e^-|z| lies in (0, 1], so log(1 + e) loses nothing to the rounding
+    // of 1 + e that matters next to max(z, 0); exponential, logarithm and
+    // reciprocal are the hardware ones (a few 1e-7 relative per term, the
+    // terms all positive).  The sums over cells are FP64.  Returns the cell's
+    // lambda.
     auto cell = [&](int r, int c, float z, float yy) -> float {
         double lam = 0.0;
         if (use_bce && r >= b0 && r <= b1 && c >= c0 && c <= c1) {
-            const float e = expf(-fabsf(z));
-            const float sp = fmaxf(z, 0.f) + log1pf(e);
-            const float sig = z >= 0.f ? 1.f / (1.f + e) : e / (1.f + e);
+            const float e = exp_hw(-fabsf(z));
+            const float sp = fmaxf(z, 0.f) + __builtin_amdgcn_logf(1.f + e) * kLn2;
+            const float sig = (z >= 0.f ? 1.f : e) * __builtin_amdgcn_rcpf(1.f + e);
             bce += (double)(sp - yy * z);
             lam += (double)(sig - yy) * invN;
         }
