@@ -533,7 +533,7 @@ int init_handle(sim_handle** out, const sim_desc* descs, int32_t n, void* worksp
                          "upload cell offsets");
     h->ib0.assign(1, 0);
     for (int i = 0; i < n; ++i)
-        h->ib0.push_back(h->ib0.back() + (int32_t)cdiv(h->L.s[i].PW, 256));
+        h->ib0.push_back(h->ib0.back() + (int32_t)cdiv(h->L.s[i].PW, 1024));   // 4 words per lane
     if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.ib0, h->ib0.data(), sizeof(int32_t) * (n + 1),
                                         hipMemcpyHostToDevice, h->st), "upload reset blocks");
     if (!rc && h->calib()) {

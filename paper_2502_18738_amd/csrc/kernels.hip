@@ -992,9 +992,7 @@ k_bbox(const DevScen* __restrict__ jobs, int32_t parity, int4* __restrict__ box)
     const int64_t PW = (int64_t)J.H * J.pitch;
     const FS_GLOBAL uint32_t* B = gmem(J.planes[parity]);
     int r0 = INT_MAX, r1 = -1, c0 = INT_MAX, c1 = -1;
-    for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < PW;
-         o += (int64_t)gridDim.x * 256) {
-        const uint32_t w = B[o];
+    auto word = [&](int64_t o, uint32_t w) {
         if (w) {
             const int r = (int)(o / J.pitch), cw = (int)(o - (int64_t)r * J.pitch);
             r0 = min(r0, r);
@@ -1002,7 +1000,21 @@ k_bbox(const DevScen* __restrict__ jobs, int32_t parity, int4* __restrict__ box)
             c0 = min(c0, 32 * cw + __builtin_ctz(w));
             c1 = max(c1, 32 * cw + 31 - __builtin_clz(w));
         }
+    };
+    // 4 words (16 bytes) per lane; the plane starts 256-byte aligned
+    const int64_t nq = PW >> 2;
+    const FS_GLOBAL fs_i4* B4 = gmem(reinterpret_cast<const fs_i4*>(J.planes[parity]));
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nq;
+         q += (int64_t)gridDim.x * 256) {
+        const fs_i4 v = B4[q];
+        if ((v.x | v.y | v.z | v.w) != 0) {
+            word(4 * q, (uint32_t)v.x);
+            word(4 * q + 1, (uint32_t)v.y);
+            word(4 * q + 2, (uint32_t)v.z);
+            word(4 * q + 3, (uint32_t)v.w);
+        }
     }
+    if (blockIdx.x == 0 && threadIdx.x < (int)(PW & 3)) word(4 * nq + threadIdx.x, B[4 * nq + threadIdx.x]);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         r0 = min(r0, __shfl_down(r0, d, 64));
@@ -1320,8 +1332,10 @@ k_prologue(int32_t H, int32_t W, int32_t pitch, const float* __restrict__ p_veg,
 __global__ void __launch_bounds__(256)
 k_init_state(const DevScen* __restrict__ jobs, const int32_t* __restrict__ ib0, int32_t n,
              int32_t nblocks) {
-    // one thread per 32-cell word: both ping-pong buffers get the initial
-    // burning plane (packed once at set-up) and an empty burned plane
+    // 4 consecutive 32-cell words per thread (a block covers 1024): both
+    // ping-pong buffers get the initial burning plane (packed once at set-up)
+    // and an empty burned plane; 16-byte accesses where the burned plane
+    // (offset PW words) is 16-byte aligned too
     int lo = 0;   // scenario s with ib0[s] <= b < ib0[s + 1]; b only grows
     {
         int hi = n;
@@ -1334,22 +1348,30 @@ k_init_state(const DevScen* __restrict__ jobs, const int32_t* __restrict__ ib0, 
         while (b >= ib0[lo + 1]) ++lo;
         const DevScen& J = jobs[lo];
         const int64_t PW = (int64_t)J.H * J.pitch;
-        const int64_t o = (int64_t)(b - ib0[lo]) * 256 + threadIdx.x;
-        if (o < PW) {
-            const uint32_t w = gmem(J.init)[o];
-            FS_GLOBAL uint32_t* p0 = gmem(J.planes[0]);
-            FS_GLOBAL uint32_t* p1 = gmem(J.planes[1]);
-            p0[o] = w;
-            p1[o] = w;
-            p0[PW + o] = 0u;
-            p1[PW + o] = 0u;
+        const int64_t o = 4 * ((int64_t)(b - ib0[lo]) * 256 + threadIdx.x);
+        FS_GLOBAL uint32_t* p0 = gmem(J.planes[0]);
+        FS_GLOBAL uint32_t* p1 = gmem(J.planes[1]);
+        if ((PW & 3) == 0 && o < PW) {
+            const fs_i4 w = *reinterpret_cast<const FS_GLOBAL fs_i4*>(gmem(J.init) + o);
+            const fs_i4 z = {0, 0, 0, 0};
+            *reinterpret_cast<FS_GLOBAL fs_i4*>(p0 + o) = w;
+            *reinterpret_cast<FS_GLOBAL fs_i4*>(p1 + o) = w;
+            *reinterpret_cast<FS_GLOBAL fs_i4*>(p0 + PW + o) = z;
+            *reinterpret_cast<FS_GLOBAL fs_i4*>(p1 + PW + o) = z;
+        } else {
+            for (int64_t e = o; e < min(o + 4, PW); ++e) {
+                const uint32_t w = gmem(J.init)[e];
+                p0[e] = w;
+                p1[e] = w;
+                p0[PW + e] = 0u;
+                p1[PW + e] = 0u;
+            }
         }
     }
 }
 
-// Calibration maps at a reset, one thread per cell: accumulator 1 on the
-// initial burning cells (a constant) and 0 elsewhere, ignition step 0 or
-// never, burn-out step never.
+// Calibration maps at a reset: accumulator 1 on the initial burning cells (a
+// constant) and 0 elsewhere, ignition step 0 or never, burn-out step never.
 // One grid row per scenario (blockIdx.y).  A thread writes 4 consecutive
 // cells with 16-byte stores (the maps of a scenario start 256-byte aligned);
 // block 0 writes the last cells of a grid whose size is not a multiple of 4.
@@ -2010,7 +2032,7 @@ hipError_t launch_bbox(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t
                        int64_t max_words, int4* box) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_bbox_clear, dim3((n + 255) / 256), dim3(256), 0, st, box, n);
-    const unsigned gx = (unsigned)std::min<int64_t>((max_words + 255) / 256, 256);
+    const unsigned gx = (unsigned)std::min<int64_t>((max_words + 1023) / 1024, 64);
     hipLaunchKernelGGL(k_bbox, dim3(gx, n), dim3(256), 0, st, d_jobs, parity, box);
     return hipGetLastError();
 }
