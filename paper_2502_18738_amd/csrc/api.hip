@@ -703,7 +703,10 @@ int enqueue_run(sim_handle* h, hipStream_t st, int T, unsigned long long* stats)
             sc.out = m + nw * ((h->lidx + 1) % 3);
             sc.clear = m + nw * ((h->lidx + 2) % 3);
         }
-        int rc = h->hip(fs::launch_step(st, h->sh, false, h->d_jobs(), h->d_tile_job(), h->ntiles,
+        // (launches over every tile of a single scenario need no tile -> job table)
+        int rc = h->hip(fs::launch_step(st, h->sh, false, h->d_jobs(),
+                                        h->n == 1 && h->ex.skip != 1 ? nullptr : h->d_tile_job(),
+                                        h->ntiles,
                                         h->parity, h->step, k, h->ex.skip, nullptr,
                                         fs::Rings{-1, 0, 0, 0}, sc, h->grid_max, stats),
                         "step kernel");

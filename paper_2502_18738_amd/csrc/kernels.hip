@@ -392,7 +392,8 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         g = xcd_tile(blockIdx.x, gridDim.x);
         if (g >= ntiles) continue;
     }
-    const DevScen& J = jobs[tile_job[g]];
+    // (launches over every tile of a single job pass no tile -> job table)
+    const DevScen& J = jobs[(!LISTED && !tile_job) ? 0 : tile_job[g]];
     const int lt = g - J.tile0;
     const int trow = lt / J.tiles_c, tcol = lt - trow * J.tiles_c;
     const int H = J.H, pitch = J.pitch;
@@ -464,6 +465,9 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         }
     }
     if (tid == 0) sFlag = 0;
+    // whether the other buffer already equals this tile (read early: a tile
+    // without fire in its region needs it right after the first barrier)
+    const uint8_t fin_lt = QUIET ? fin[lt] : 0;
     bool myb = false;
 #pragma unroll
     for (int i = 0; i < WPT; ++i) {
@@ -839,7 +843,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
 
     if (QUIET && quiet) {
         // as a skipped tile: the other buffer is brought up to date once
-        if (!(fin[lt] & 2)) {
+        if (!(fin_lt & 2)) {
 #pragma unroll
             for (int i = 0; i < WPT; ++i) {
                 const int w = tid + i * NT;
