@@ -37,7 +37,7 @@ struct ScenLayout {
 };
 
 struct Layout {
-    size_t err, stats, box, part, jobs, tile_job, adj_jobs, adj_tile_job, gpart, ranges, lam,
+    size_t err, stats, box, part, jobs, tile_job, adj_jobs, adj_tile_job, sm8, lam,
         cell0, bl0, ib0, gpart_tmap, masks, adj_masks, tielog, tie_n, fbox, qbox, cell0q, total;
     int32_t mask_words, adj_mask_words;
     int64_t total_cells;
@@ -112,7 +112,7 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
             s.ckpt = take(8 * (size_t)s.PW * (size_t)L->nseg);
         }
     }
-    L->adj_jobs = L->adj_tile_job = L->gpart = L->ranges = L->lam = L->bl0 = L->gpart_tmap = 0;
+    L->adj_jobs = L->adj_tile_job = L->sm8 = L->lam = L->bl0 = L->gpart_tmap = 0;
     L->adj_masks = 0;
     L->adj_mask_words = 0;
     L->tmap_blocks = 0;
@@ -127,11 +127,12 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         L->adj_tile_job = take(sizeof(int32_t) * (size_t)L->adj_max_tiles_total);
         L->adj_mask_words = (int32_t)cdiv(L->adj_max_tiles_total, 64);
         L->adj_masks = take(3 * 8 * (size_t)L->adj_mask_words);
-        L->gpart = take(4 * sizeof(double) * (size_t)L->adj_max_tiles_total);
-        L->ranges = take(sizeof(int32_t) * (size_t)(n + 1));
         int64_t cells = 0;
         for (int i = 0; i < n; ++i) cells += (int64_t)d[i].H * d[i].W;
         L->lam = take(4 * (size_t)cells);   // dL/dyhat of all scenarios, concatenated
+        // burning-slot masks recorded by the checkpoint adjoint's recompute, one
+        // byte per cell, concatenated like lam (cleared in 32-bit words)
+        L->sm8 = take(4 * (size_t)cdiv(cells, 4));
         int64_t blocks = 0;
         for (int i = 0; i < n; ++i) blocks += cdiv((int64_t)d[i].H * d[i].W, 256);
         L->tmap_blocks = (int32_t)blocks;
@@ -215,7 +216,7 @@ struct sim_handle {
     std::vector<int32_t> tile_job;
     int32_t ntiles = 0;
     std::vector<fs::DevScen> adj;   // adjoint jobs for the last run length
-    std::vector<int32_t> adj_tile_job, adj_ranges;
+    std::vector<int32_t> adj_tile_job;
     int32_t adj_ntiles = 0, adj_T = -1;
     sim_exec ex{};
     fs::TileShape sh{};
@@ -494,7 +495,7 @@ int init_handle(sim_handle** out, const sim_desc* descs, int32_t n, void* worksp
         J.tign = h->calib() ? reinterpret_cast<int32_t*>(h->ws + s.tign) : nullptr;
         J.tout = h->calib() ? reinterpret_cast<int32_t*>(h->ws + s.tout) : nullptr;
         J.ckpt = h->calib() ? reinterpret_cast<uint32_t*>(h->ws + s.ckpt) : nullptr;
-        J.gpart = nullptr;
+        J.sm8 = nullptr;   // set below with lam_off
         J.lam_off = 0;   // set below: offset of this scenario's grid in dL/dyhat
         h->max_words = std::max<int64_t>(h->max_words, s.PW);
     }
@@ -527,7 +528,10 @@ int init_handle(sim_handle** out, const sim_desc* descs, int32_t n, void* worksp
                     "keep initial state");
     h->cell0.assign(1, 0);
     for (int i = 0; i < n; ++i) h->cell0.push_back(h->cell0.back() + (int64_t)descs[i].H * descs[i].W);
-    for (int i = 0; i < n; ++i) h->job[i].lam_off = h->cell0[i];
+    for (int i = 0; i < n; ++i) {
+        h->job[i].lam_off = h->cell0[i];
+        if (h->calib()) h->job[i].sm8 = reinterpret_cast<uint8_t*>(h->ws + h->L.sm8) + h->cell0[i];
+    }
     if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.cell0, h->cell0.data(),
                                         sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, h->st),
                          "upload cell offsets");
@@ -1029,7 +1033,6 @@ int build_adjoint(sim_handle* h, int T) {
     const int nseg = (int)cdiv(T, h->ckpt_every);
     h->adj.clear();
     h->adj_tile_job.clear();
-    h->adj_ranges.assign(1, 0);
     int32_t g = 0;
     for (int i = 0; i < h->n; ++i) {
         const fs::DevScen& F = h->job[i];
@@ -1045,14 +1048,12 @@ int build_adjoint(sim_handle* h, int T) {
             J.t_end = std::min((sg + 1) * h->ckpt_every, T);
             J.yhat = nullptr;
             J.tign = J.tout = nullptr;
-            J.gpart = reinterpret_cast<double*>(h->ws + h->L.gpart);
             J.tile0 = g;
             const int32_t nt = J.tiles_r * J.tiles_c;
             h->adj_tile_job.insert(h->adj_tile_job.end(), nt, (int32_t)h->adj.size());
             g += nt;
             h->adj.push_back(J);
         }
-        h->adj_ranges.push_back(g);
     }
     int64_t off = 0;
     for (int i = 0; i < h->n; ++i) {
@@ -1066,9 +1067,6 @@ int build_adjoint(sim_handle* h, int T) {
     if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.adj_tile_job, h->adj_tile_job.data(),
                                         sizeof(int32_t) * (size_t)g, hipMemcpyHostToDevice,
                                         h->st), "upload adjoint tiles");
-    if (!rc) rc = h->hip(hipMemcpyAsync(h->ws + h->L.ranges, h->adj_ranges.data(),
-                                        sizeof(int32_t) * (size_t)(h->n + 1),
-                                        hipMemcpyHostToDevice, h->st), "upload ranges");
     if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
     if (!rc) h->adj_T = T;
     return rc;
@@ -1086,17 +1084,17 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
     rg.T = T;
     // both adjoints read the q8 table of the run's parameters
     if (int rc = ensure_qtable(h, T)) return rc;
-    if (h->adj_method == 1) {
+    // gradient pass over every cell (per-block FP64 partials, then a fixed-order
+    // reduction per scenario)
+    auto gradient_pass = [&](bool from_maps) {
         auto* gp = reinterpret_cast<double*>(h->ws + h->L.gpart_tmap);
-        int rc = h->hip(fs::launch_adjoint_tmap(h->st, h->d_jobs(),
-                                                reinterpret_cast<const int32_t*>(h->ws + h->L.bl0),
-                                                h->n, h->L.tmap_blocks, lam, rg, gp),
-                        "time-map adjoint");
-        if (!rc) rc = h->hip(fs::launch_grad_reduce(h->st, gp,
-                                                    reinterpret_cast<int32_t*>(h->ws + h->L.bl0),
-                                                    h->n, grad), "reduce gradient");
-        return rc;
-    }
+        const auto* bl0 = reinterpret_cast<const int32_t*>(h->ws + h->L.bl0);
+        int r = h->hip(fs::launch_adjoint_cells(h->st, h->d_jobs(), bl0, h->n, h->L.tmap_blocks,
+                                                lam, rg, gp, from_maps), "adjoint gradient");
+        if (!r) r = h->hip(fs::launch_grad_reduce(h->st, gp, bl0, h->n, grad), "reduce gradient");
+        return r;
+    };
+    if (h->adj_method == 1) return gradient_pass(true);
     int rc = SIM_OK;
     if (h->adj_T != T) rc = build_adjoint(h, T);
     if (rc) return rc;
@@ -1112,8 +1110,11 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
         rc = h->hip(fs::launch_mask_init(h->st, d_adj, d_adj_tiles, h->adj_ntiles, 0, amask,
                                          h->L.adj_mask_words), "adjoint worklist");
     int alidx = 0;
-    if (!rc) rc = h->hip(fs::launch_fill_u32(h->st, reinterpret_cast<uint32_t*>(h->ws + h->L.gpart),
-                                             (size_t)h->adj_ntiles * 8, 0u), "zero partials");
+    // the recompute records the burning slots of each cell it ignites at an
+    // attached step; the gradient pass evaluates the cells with a record
+    if (!rc) rc = h->hip(fs::launch_fill_u32(h->st, reinterpret_cast<uint32_t*>(h->ws + h->L.sm8),
+                                             (size_t)cdiv(h->cell0.back(), 4), 0u),
+                         "clear slot records");
     int parity = 0;
     unsigned long long* stats = nullptr;
     for (int off = 0; off < h->ckpt_every && !rc; ) {
@@ -1126,14 +1127,13 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
         }
         ++alidx;
         rc = h->hip(fs::launch_step(h->st, h->sh, true, d_adj, d_adj_tiles, h->adj_ntiles,
-                                    parity, off, k, h->ex.skip, lam, rg, sc, h->grid_max, stats),
-                    "adjoint kernel");
+                                    parity, off, k, h->ex.skip, nullptr, rg, sc, h->grid_max,
+                                    stats),
+                    "adjoint recompute");
         parity ^= 1;
         off += k;
     }
-    if (!rc) rc = h->hip(fs::launch_grad_reduce(h->st, reinterpret_cast<double*>(h->ws + h->L.gpart),
-                                                reinterpret_cast<int32_t*>(h->ws + h->L.ranges),
-                                                h->n, grad), "reduce gradient");
+    if (!rc) rc = gradient_pass(false);
     return rc;
 }
 

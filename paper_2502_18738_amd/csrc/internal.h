@@ -47,7 +47,9 @@ struct DevScen {
     int32_t* tign;             // step each cell ignited (0: initially burning) or nullptr
     int32_t* tout;             // step each cell burnt out, or nullptr
     uint32_t* ckpt;            // checkpoint store (forward) / own segment (adjoint)
-    double* gpart;             // per-tile gradient partials (adjoint jobs)
+    uint8_t* sm8;              // burning slots of each cell that ignited at an attached
+                               // step, recorded by the checkpoint adjoint's recompute
+                               // (0: none); nullptr outside calibration
     int64_t lam_off;           // offset of this scenario's dL/dyhat grid
     void* tielog;              // near-tie records (sim_tie layout) or nullptr
     unsigned long long* tie_n; // number of trials logged
@@ -134,9 +136,13 @@ hipError_t launch_init_state(hipStream_t st, const DevScen* d_jobs, const int32_
                              int64_t total_cells, bool maps);
 // Time-map adjoint: one pass over every cell of every scenario; bl0 = n + 1
 // prefix sums of ceil(cells / 256) per scenario; writes gpart[block][4].
-hipError_t launch_adjoint_tmap(hipStream_t st, const DevScen* d_jobs, const int32_t* d_bl0,
-                               int32_t n, int32_t nblocks, const float* lam, Rings rings,
-                               double* gpart);
+// Gradient pass of the adjoints: per-block FP64 partials of
+// lambda_j * d p_ignite_j / d theta over the cells that ignited at attached
+// steps, their burning slots from the ignition / burn-out maps (from_maps,
+// time-map adjoint) or from the slot masks the recompute recorded (sm8).
+hipError_t launch_adjoint_cells(hipStream_t st, const DevScen* d_jobs, const int32_t* d_bl0,
+                                int32_t n, int32_t nblocks, const float* lam, Rings rings,
+                                double* gpart, bool from_maps);
 hipError_t launch_set_state(hipStream_t st, const DevScen& job, const uint8_t* in,
                             uint32_t* planes, int* d_err);
 hipError_t launch_get_state(hipStream_t st, const DevScen& job, const uint32_t* planes,
@@ -184,7 +190,7 @@ hipError_t launch_pignite(hipStream_t st, const DevScen* d_job, const DevScen& j
 hipError_t launch_loss(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
                        int32_t max_h, const uint8_t* y, int32_t kind, float* lambda, int* d_box,
                        double* d_part, double* loss_out);
-// grad[s] = sum of gpart[g] over tiles g in [ranges[s], ranges[s+1]).
+// grad[s] = sum of gpart[g] over blocks g in [ranges[s], ranges[s+1]).
 hipError_t launch_grad_reduce(hipStream_t st, const double* gpart, const int32_t* d_ranges,
                               int32_t n, double* grad);
 hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, size_t n, uint32_t v);

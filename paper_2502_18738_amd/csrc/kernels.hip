@@ -295,7 +295,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 template <int TR, int TC, int KM, bool ADJ, int NT, bool LISTED>
 constexpr int step_waves() {
     constexpr int wpt = ((TR + 2 * KM) * (TC + 2) + NT - 1) / NT;
-    return NT >= 512 ? 1 : (ADJ || LISTED) ? 5 : (wpt <= 2 ? 8 : 7);
+    return NT >= 512 ? 1 : LISTED ? 5 : (wpt <= 2 ? 8 : 7);
 }
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Wpass-failed"
@@ -344,7 +344,6 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     // nearly always hold some, so they skip the test
     constexpr bool QUIET = !LISTED;
     __shared__ int sAny[QUIET ? NWAVE : 1];   // per wavefront: a loaded word holds a burning cell
-    __shared__ double sG[ADJ ? NWAVE * 4 : 1];
 
     const int tid = threadIdx.x;
 
@@ -494,7 +493,6 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     const bool has_yhat = !ADJ && J.yhat != nullptr, has_tign = !ADJ && J.tign != nullptr,
                has_tout = !ADJ && J.tout != nullptr, has_tlog = !ADJ && J.tielog != nullptr;
     const bool counting = stats != nullptr;   // trial and near-tie counters
-    double gsum[4] = {0.0, 0.0, 0.0, 0.0};
     unsigned long long n_trials = 0, n_ties = 0;
     int cur = 0;
 
@@ -676,8 +674,9 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             // at the start of the run).  Each lane takes up to R trials per pass
             // and issues all of their gathers before deciding.  The adjoint
             // recompute takes the same decisions from the same values and, for
-            // the cells that ignite inside the tile at an attached step, adds
-            // lambda_j * d p_ignite_j / d theta (Eq. 2-5 and 9 differentiated).
+            // the cells that ignite inside the tile at an attached step,
+            // records their burning slots (the gradient pass then adds
+            // lambda_j * d p_ignite_j / d theta from them).
             // one trial per lane per pass: a busy tile rarely has more trials
             // than lanes, and fewer registers mean more resident wavefronts
             // (2 and 4 trials per lane measured slower on every workload)
@@ -690,9 +689,6 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
             for (int k0 = c0; k0 < cend; k0 += R * NT) {
                 int ent[R], ign[R];
                 fs_f4 qa[R], qb[R];
-                fs_f4 ta[R], tb[R];   // adjoint only
-                float4 rc[R];
-                float lj[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     if (k0 + r * NT >= cend) break;   // uniform: no lane has trial r
@@ -701,27 +697,12 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                     ign[r] = (ent[r] >> 15) & 1;
                     ent[r] &= 0x7FFF;
                     qa[r] = qb[r] = (fs_f4)(0.f);
-                    if constexpr (ADJ) {
-                        ta[r] = tb[r] = (fs_f4)(0.f);
-                        rc[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-                        lj[r] = 0.f;
-                    }
                     if (k < cend && ign[r]) {
                         const int w = ent[r] >> 5, bit = ent[r] & 31;
                         const int lr = w / RC, lc = w - (w / RC) * RC;
                         const int64_t j = jbase + (lr * Wg + lc * 32 + bit);
                         qa[r] = q8v[2 * j];
                         qb[r] = q8v[2 * j + 1];
-                        if constexpr (ADJ) {
-                            if (att && lr >= KM && lr < KM + TR && lc >= 1 && lc <= TC) {
-                                // (adjoint-only fields: read where used)
-                                const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
-                                ta[r] = t8v[2 * j];
-                                tb[r] = t8v[2 * j + 1];
-                                rc[r] = load_f4(J.rec, j);
-                                lj[r] = lam[J.lam_off + j];
-                            }
-                        }
                     }
                 }
 #pragma unroll
@@ -791,14 +772,12 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
                         if (interior && has_tign) gmem(J.tign)[j] = t;
                         if constexpr (ADJ) {
                             if (interior && att) {
-                                uint32_t sm = 0;   // burning slots
+                                // the cell's burning slots at t - 1: all the
+                                // gradient pass needs of the recomputed state
+                                uint32_t sm = 0;
 #pragma unroll
                                 for (int m = 0; m < 8; ++m) sm |= ((nm[m] >> bit) & 1u) << m;
-                                float gl[4];
-                                pignite_grad_tab(EdgeParams{J.p_h, J.a, J.c1, J.c2, J.c}, rc[r],
-                                                 ta[r], tb[r], sm, q, gl);
-#pragma unroll
-                                for (int m = 0; m < 4; ++m) gsum[m] += (double)(lj[r] * gl[m]);
+                                gmem(J.sm8)[j] = (uint8_t)sm;
                             }
                         }
                     }
@@ -890,26 +869,10 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     if (anyB) atomicOr(&sFlag, 1);
     if (changed) atomicOr(&sFlag, 2);
 
-    if (ADJ) {
-        // deterministic work-group sum of the per-lane FP64 partials
-        for (int m = 0; m < 4; ++m) {
-            double v = gsum[m];
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
-            if ((tid & 63) == 0) sG[(tid >> 6) * 4 + m] = v;
-        }
-    }
     __syncthreads();
     if (tid == 0) {
         const int f = sFlag;
         fout[lt] = (uint8_t)(((f & 1) ? 1 : 0) | ((f & 2) ? 0 : 2));
-        if (ADJ) {
-            for (int m = 0; m < 4; ++m) {
-                double acc = 0.0;
-                for (int v = 0; v < NWAVE; ++v) acc += sG[v * 4 + m];
-                gmem(J.gpart)[(int64_t)g * 4 + m] += acc;
-            }
-        }
     }
     if (stats) {
         // per-wave reduction of the counters, one atomic per wave
@@ -1431,15 +1394,20 @@ k_init_maps(const DevScen* __restrict__ jobs) {
     }
 }
 
-// Time-map adjoint: for every cell j that ignited at step t_j >= 1 of an
-// attached step, rebuild its burning neighbours at t_j - 1 from the maps
-// (neighbour i burned then iff tign_i <= t_j - 1 < tout_i) and add
-// lambda_j * d p_ignite_j / d theta.  One block covers cells of one scenario;
-// gpart[block] receives the block's FP64 sum in a fixed order.
+// Gradient pass of both adjoints: for every cell j that ignited at an
+// attached step, lambda_j * d p_ignite_j / d theta with the burning
+// neighbours of j at its ignition step held constant (Eq. 2-5 and 9
+// differentiated).  FROM_MAPS (time-map adjoint): j ignited at t_j >= 1 and
+// neighbour i burned at t_j - 1 iff tign_i <= t_j - 1 < tout_i.  Otherwise
+// (checkpoint adjoint) the recompute recorded the burning slots of each such
+// cell in sm8 (0: no ignition at an attached step).
+// One block covers cells of one scenario; gpart[block] receives the block's
+// FP64 sum in a fixed order.
+template <bool FROM_MAPS>
 __global__ void __launch_bounds__(256)
-k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0, int32_t n,
-               const float* __restrict__ lam, Rings rings, double* __restrict__ gpart,
-               int32_t nblocks) {
+k_adjoint_cells(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0, int32_t n,
+                const float* __restrict__ lam, Rings rings, double* __restrict__ gpart,
+                int32_t nblocks) {
     __shared__ double sh[4][256];
     // a fixed grid walks the nblocks segments of 256 cells; each segment's
     // partial sums go to its own slot, so the reduction order is fixed
@@ -1457,21 +1425,27 @@ k_adjoint_tmap(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0
     const int64_t j = (int64_t)(b - bl0[lo]) * 256 + threadIdx.x;
     double g[4] = {0.0, 0.0, 0.0, 0.0};
     if (j < (int64_t)J.H * J.W) {
-        const int tj = J.tign[j];
-        if (tj >= 1 && tj <= rings.T && attached(rings, tj)) {
-            const int r = (int)(j / J.W), c = (int)(j - (int64_t)r * J.W);
-            // burning neighbours at tj - 1: ignited by then and not yet out
-            uint32_t sm = 0;
+        uint32_t sm = 0;   // burning slots of j at its ignition step
+        if constexpr (FROM_MAPS) {
+            const int tj = J.tign[j];
+            if (tj >= 1 && tj <= rings.T && attached(rings, tj)) {
+                const int r = (int)(j / J.W), c = (int)(j - (int64_t)r * J.W);
+                // burning neighbours at tj - 1: ignited by then and not yet out
 #pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                int dr, dc;
-                slot_dir(m, dr, dc);
-                const int rr = r + dr, cc = c + dc;
-                if (rr >= 0 && rr < J.H && cc >= 0 && cc < J.W) {
-                    const int64_t i = (int64_t)rr * J.W + cc;
-                    if (J.tign[i] <= tj - 1 && tj - 1 < J.tout[i]) sm |= 1u << m;
+                for (int m = 0; m < 8; ++m) {
+                    int dr, dc;
+                    slot_dir(m, dr, dc);
+                    const int rr = r + dr, cc = c + dc;
+                    if (rr >= 0 && rr < J.H && cc >= 0 && cc < J.W) {
+                        const int64_t i = (int64_t)rr * J.W + cc;
+                        if (J.tign[i] <= tj - 1 && tj - 1 < J.tout[i]) sm |= 1u << m;
+                    }
                 }
             }
+        } else {
+            sm = J.sm8[j];
+        }
+        if (sm) {
             const float4 qa = load_f4(J.q8, 2 * j), qb = load_f4(J.q8, 2 * j + 1);
             const float qv[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
             float q[8];
@@ -1588,8 +1562,9 @@ __global__ void k_fill_u32(uint32_t* p, size_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
-// Deterministic per-scenario sum of the per-tile partials of the adjoint:
-// one work-group per scenario, fixed lane striding and a fixed tree.
+// Deterministic per-scenario sum of the per-block partials of the adjoint's
+// gradient pass (ranges: the scenarios' block ranges): one work-group per
+// scenario, fixed lane striding and a fixed tree.
 __global__ void __launch_bounds__(256)
 k_grad_reduce(const double* __restrict__ gpart, const int32_t* __restrict__ ranges,
               double* __restrict__ grad) {
@@ -2086,12 +2061,16 @@ hipError_t launch_dup_planes(hipStream_t st, const DevScen* d_jobs, int32_t n, i
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_tmap(hipStream_t st, const DevScen* d_jobs, const int32_t* d_bl0,
-                               int32_t n, int32_t nblocks, const float* lam, Rings rings,
-                               double* gpart) {
+hipError_t launch_adjoint_cells(hipStream_t st, const DevScen* d_jobs, const int32_t* d_bl0,
+                                int32_t n, int32_t nblocks, const float* lam, Rings rings,
+                                double* gpart, bool from_maps) {
     if (nblocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adjoint_tmap, dim3(std::min(nblocks, 16384)), dim3(256), 0, st, d_jobs,
-                       d_bl0, n, lam, rings, gpart, nblocks);
+    if (from_maps)
+        hipLaunchKernelGGL(k_adjoint_cells<true>, dim3(std::min(nblocks, 16384)), dim3(256), 0,
+                           st, d_jobs, d_bl0, n, lam, rings, gpart, nblocks);
+    else
+        hipLaunchKernelGGL(k_adjoint_cells<false>, dim3(std::min(nblocks, 16384)), dim3(256), 0,
+                           st, d_jobs, d_bl0, n, lam, rings, gpart, nblocks);
     return hipGetLastError();
 }
 
