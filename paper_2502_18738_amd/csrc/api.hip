@@ -134,7 +134,7 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
         // byte per cell, concatenated like lam (cleared in 32-bit words)
         L->sm8 = take(4 * (size_t)cdiv(cells, 4));
         int64_t blocks = 0;
-        for (int i = 0; i < n; ++i) blocks += cdiv((int64_t)d[i].H * d[i].W, 256);
+        for (int i = 0; i < n; ++i) blocks += cdiv((int64_t)d[i].H * d[i].W, 1024);   // gradient-pass segments
         L->tmap_blocks = (int32_t)blocks;
         L->bl0 = take(sizeof(int32_t) * (size_t)(n + 1));
         L->gpart_tmap = take(4 * sizeof(double) * (size_t)blocks);
@@ -543,7 +543,7 @@ int init_handle(sim_handle** out, const sim_desc* descs, int32_t n, void* worksp
     if (!rc && h->calib()) {
         h->bl0.assign(1, 0);
         for (int i = 0; i < n; ++i)
-            h->bl0.push_back(h->bl0.back() + (int32_t)cdiv((int64_t)descs[i].H * descs[i].W, 256));
+            h->bl0.push_back(h->bl0.back() + (int32_t)cdiv((int64_t)descs[i].H * descs[i].W, 1024));
         rc = h->hip(hipMemcpyAsync(h->ws + h->L.bl0, h->bl0.data(), sizeof(int32_t) * (n + 1),
                                    hipMemcpyHostToDevice, h->st), "upload block offsets");
     }

@@ -1401,16 +1401,17 @@ k_init_maps(const DevScen* __restrict__ jobs) {
 // neighbour i burned at t_j - 1 iff tign_i <= t_j - 1 < tout_i.  Otherwise
 // (checkpoint adjoint) the recompute recorded the burning slots of each such
 // cell in sm8 (0: no ignition at an attached step).
-// One block covers cells of one scenario; gpart[block] receives the block's
+// A segment of 1024 cells lies in one scenario; gpart[segment] receives its
 // FP64 sum in a fixed order.
 template <bool FROM_MAPS>
 __global__ void __launch_bounds__(256)
 k_adjoint_cells(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0, int32_t n,
                 const float* __restrict__ lam, Rings rings, double* __restrict__ gpart,
                 int32_t nblocks) {
-    __shared__ double sh[4][256];
-    // a fixed grid walks the nblocks segments of 256 cells; each segment's
-    // partial sums go to its own slot, so the reduction order is fixed
+    __shared__ double sh[4][4];   // per wavefront, per parameter
+    // a fixed grid walks the nblocks segments of 1024 cells (4 per lane, in
+    // four coalesced passes); each segment's partial sums go to its own slot,
+    // and every sum runs in a fixed order
     int lo = 0;   // scenario s with bl0[s] <= b < bl0[s + 1]; b only grows
     {
         int hi = n;
@@ -1422,8 +1423,9 @@ k_adjoint_cells(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl
     for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
     while (b >= bl0[lo + 1]) ++lo;
     const DevScen& J = jobs[lo];
-    const int64_t j = (int64_t)(b - bl0[lo]) * 256 + threadIdx.x;
     double g[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < 4; ++e) {
+    const int64_t j = (int64_t)(b - bl0[lo]) * 1024 + e * 256 + threadIdx.x;
     if (j < (int64_t)J.H * J.W) {
         uint32_t sm = 0;   // burning slots of j at its ignition step
         if constexpr (FROM_MAPS) {
@@ -1457,18 +1459,23 @@ k_adjoint_cells(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl
                              t8v[2 * j], t8v[2 * j + 1], sm, q, gl);
             const float lj = lam[J.lam_off + j];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) g[m] = (double)(lj * gl[m]);
+            for (int m = 0; m < 4; ++m) g[m] += (double)(lj * gl[m]);
         }
     }
-#pragma unroll
-    for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] = g[m];
-    __syncthreads();
-    for (int d = 128; d >= 1; d >>= 1) {
-        if (threadIdx.x < d)
-            for (int m = 0; m < 4; ++m) sh[m][threadIdx.x] += sh[m][threadIdx.x + d];
-        __syncthreads();
     }
-    if (threadIdx.x < 4) gpart[(int64_t)b * 4 + threadIdx.x] = sh[threadIdx.x][0];
+    // wavefront sums by shuffles, then the 4 wavefronts in order
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        double v = g[m];
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
+        if (lane == 0) sh[wv][m] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 4)
+        gpart[(int64_t)b * 4 + threadIdx.x] =
+            ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
     __syncthreads();   // sh is reused by the next segment
     }
 }
