@@ -258,11 +258,12 @@ SIM_API int sim_adjoint(sim_handle* h, const float* dL_dyhat, double* grad);
 
 /* Adjoint used by sim_adjoint and sim_loss_grad.
  *   SIM_ADJ_CHECKPOINT (default): recompute every checkpoint segment of the
- *     last run (all segments of all scenarios in one launch sequence).
- *   SIM_ADJ_TIMEMAP: one pass over the cells; the forward records each
- *     cell's ignition and burn-out steps, from which the burning neighbours
- *     at t_j - 1 of every ignited cell j are rebuilt exactly.
- * Both return the same gradient (up to the order of the FP64 sums).
+ *     last run (all segments of all scenarios in one launch sequence),
+ *     recording the burning neighbours at t_j - 1 of every cell j it ignites.
+ *   SIM_ADJ_TIMEMAP: no recompute; the forward records each cell's ignition
+ *     and burn-out steps, from which those neighbours are rebuilt exactly.
+ * Both then evaluate the same per-cell terms in one pass over the cells,
+ * summed in the same fixed order.
  * Step rings (Sec. 2.3, "update by step rings"): only cells ignited at an
  * attached step contribute -- steps 1..r_first, the last r_last steps, and
  * r_between steps spread evenly in between (step r_first + round(k * span /
