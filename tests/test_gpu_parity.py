@@ -686,8 +686,11 @@ def test_adjoint_methods_and_step_rings_match_oracle(Sim, rings):
     for method in ("checkpoint", "timemap"):
         sim.set_adjoint(method, rings)
         grads[method] = sim.adjoint(lam_t).cpu().numpy()
-    np.testing.assert_allclose(grads["timemap"], grads["checkpoint"], rtol=1e-5,
-                               atol=1e-6 * np.abs(grads["checkpoint"]).max())
+    # both adjoints evaluate the same per-cell terms (burning slots recorded
+    # by the recompute, or rebuilt from the maps) in one pass, summed in the
+    # same order: the gradients agree bit for bit
+    assert np.array_equal(grads["timemap"], grads["checkpoint"]), (grads["timemap"],
+                                                                    grads["checkpoint"])
     for b, s in enumerate(scs):
         r = oracle.run(s, T, want_tstep=True)
         assert np.array_equal(gstate(sim, b), r["S"])
