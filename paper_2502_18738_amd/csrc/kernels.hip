@@ -286,12 +286,12 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // 256-lane shapes serve many busy tiles at once (ensembles, calibration): they
 // keep no per-word slot masks in LDS (see SN below), so that more work-groups
 // fit a CU, and they aim at a register budget per wavefront: 64 registers (8
-// wavefronts per SIMD) for launches over every tile with up to 2 words per
-// lane, 72 (7) for those with more, 96 (5) for worklist and adjoint launches,
-// whose longer-lived state would spill below that (measured: the tighter
-// targets gain 2-4 % on calibration and the ensemble).  Where a shape cannot
-// reach its target the compiler settles on the occupancy it can reach (its
-// warning is silenced).
+// wavefronts per SIMD) for launches over every tile (the adjoint recompute
+// among them) with up to 2 words per lane, 72 (7) for those with more, 96 (5)
+// for worklist launches, whose longer-lived state would spill below that
+// (measured: the tighter targets gain 2-4 % on calibration and the ensemble).
+// Where a shape cannot reach its target the compiler settles on the occupancy
+// it can reach (its warning is silenced).
 template <int TR, int TC, int KM, bool ADJ, int NT, bool LISTED>
 constexpr int step_waves() {
     constexpr int wpt = ((TR + 2 * KM) * (TC + 2) + NT - 1) / NT;
