@@ -206,6 +206,41 @@ def test_dense_fire_takes_the_trial_list_in_chunks(Sim, ex):
     check_light_cone(gstate(sim), states, ties, T)
 
 
+@pytest.mark.parametrize("ex", CHUNK_SHAPES, ids=lambda e: "%dx%dd%ds%d" % (
+    e["tile_rows"], e["tile_words"], e["depth"], int(e["skip"])))
+def test_dense_fire_gradient_matches_oracle(Sim, ex):
+    """Calibration from a burning block: the adjoint recompute places and
+    takes its trials in chunks as well.  Loss and checkpoint-adjoint gradient
+    against the oracle, and the time-map adjoint bit for bit (this seed has
+    no near tie)."""
+    import torch
+    H, W, T = 160, 288, 8
+    s = synth.make_lakes(H, W, 31, T=T)
+    init = np.zeros((H, W), dtype=s.init_burning.dtype)
+    init[10:150, 12:276] = 1
+    init[s.p_veg <= -1.0] = 0
+    s = dataclasses.replace(s, init_burning=init, seed=731)
+    y = (oracle.run(s.with_params(0.7, 0.05, 0.06, 0.1), T)["S"] != 0).astype(np.uint8)
+    sim = Sim([s], calib=True, T_max=T, ckpt_every=4, exec=ex)
+    sim.run(T)
+    loss, grad = sim.loss_grad(y.ravel(), 0)
+    loss, grad = loss.cpu().numpy(), grad.cpu().numpy()
+    r = oracle.run(s, T, want_yhat=True, tie_eps=TIE)
+    assert r["ties"] == 0
+    assert_same_trajectory(gstate(sim), r["S"], "dense fire")
+    L, lam = oracle.loss(r["yhat"], y, 0)
+    assert loss[0] == pytest.approx(L, rel=1e-6)
+    g = oracle.grad(s, T, lam)
+    scale = np.abs(g).max()
+    assert np.all(np.abs(grad[0] - g) <= 1e-4 * np.abs(g) + 1e-6 * scale), (grad[0], g)
+    lam_t = torch.from_numpy(lam.astype(np.float32).ravel())
+    gc = sim.adjoint(lam_t).cpu().numpy()
+    sim.set_adjoint("timemap")
+    gt = sim.adjoint(lam_t).cpu().numpy()
+    assert np.array_equal(gc, gt), (gc, gt)
+    say("dense fire gradient", ex, grad[0], "oracle", g)
+
+
 def test_blocked_run_equals_oracle_final_state(Sim):
     """A temporally blocked, tile-skipping run reaches the oracle's final state
     (up to near-tie flips inside their light cones)."""
