@@ -1402,16 +1402,24 @@ k_init_maps(const DevScen* __restrict__ jobs) {
 // (checkpoint adjoint) the recompute recorded the burning slots of each such
 // cell in sm8 (0: no ignition at an attached step).
 // A segment of 1024 cells lies in one scenario; gpart[segment] receives its
-// FP64 sum in a fixed order.
+// FP64 sum in a fixed order.  A lane first tests 4 consecutive cells; the
+// cells that ignited at an attached step are listed in cell order (a scan),
+// and the lanes then take the list, so that the reads and the arithmetic of
+// the gradient run on dense wavefronts.  Both adjoints list the same cells
+// (an ignition needs a burning neighbour, and calibration handles take no
+// ignitions or states from outside), so they add the same terms in the same
+// order.
 template <bool FROM_MAPS>
 __global__ void __launch_bounds__(256)
 k_adjoint_cells(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl0, int32_t n,
                 const float* __restrict__ lam, Rings rings, double* __restrict__ gpart,
                 int32_t nblocks) {
     __shared__ double sh[4][4];   // per wavefront, per parameter
-    // a fixed grid walks the nblocks segments of 1024 cells (4 per lane, in
-    // four coalesced passes); each segment's partial sums go to its own slot,
-    // and every sum runs in a fixed order
+    __shared__ int sWave[4];
+    __shared__ uint16_t sOff[1024];   // listed cells: offset in the segment
+    __shared__ uint32_t sVal[1024];   // and t_j (FROM_MAPS) or the burning slots
+    // a fixed grid walks the nblocks segments of 1024 cells; each segment's
+    // partial sums go to its own slot, and every sum runs in a fixed order
     int lo = 0;   // scenario s with bl0[s] <= b < bl0[s + 1]; b only grows
     {
         int hi = n;
@@ -1423,60 +1431,108 @@ k_adjoint_cells(const DevScen* __restrict__ jobs, const int32_t* __restrict__ bl
     for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
     while (b >= bl0[lo + 1]) ++lo;
     const DevScen& J = jobs[lo];
-    double g[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int e = 0; e < 4; ++e) {
-    const int64_t j = (int64_t)(b - bl0[lo]) * 1024 + e * 256 + threadIdx.x;
-    if (j < (int64_t)J.H * J.W) {
-        uint32_t sm = 0;   // burning slots of j at its ignition step
-        if constexpr (FROM_MAPS) {
-            const int tj = J.tign[j];
-            if (tj >= 1 && tj <= rings.T && attached(rings, tj)) {
-                const int r = (int)(j / J.W), c = (int)(j - (int64_t)r * J.W);
-                // burning neighbours at tj - 1: ignited by then and not yet out
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    int dr, dc;
-                    slot_dir(m, dr, dc);
-                    const int rr = r + dr, cc = c + dc;
-                    if (rr >= 0 && rr < J.H && cc >= 0 && cc < J.W) {
-                        const int64_t i = (int64_t)rr * J.W + cc;
-                        if (J.tign[i] <= tj - 1 && tj - 1 < J.tout[i]) sm |= 1u << m;
-                    }
-                }
-            }
+    const int64_t cells = (int64_t)J.H * J.W;
+    const int64_t j0 = (int64_t)(b - bl0[lo]) * 1024;
+    const int64_t jq = j0 + 4 * threadIdx.x;   // this lane's 4 cells
+    uint32_t v[4];   // per cell: t_j or its burning slots; 0 = not listed
+    if constexpr (FROM_MAPS) {
+        int t[4] = {0, 0, 0, 0};
+        if (jq + 4 <= cells) {   // a scenario's maps start 256-byte aligned
+            const fs_i4 x = *reinterpret_cast<const FS_GLOBAL fs_i4*>(gmem(J.tign) + jq);
+            t[0] = x.x; t[1] = x.y; t[2] = x.z; t[3] = x.w;
         } else {
-            sm = J.sm8[j];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (jq + e < cells) t[e] = gmem(J.tign)[jq + e];
         }
-        if (sm) {
-            const float4 qa = load_f4(J.q8, 2 * j), qb = load_f4(J.q8, 2 * j + 1);
-            const float qv[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
-            float q[8];
 #pragma unroll
-            for (int m = 0; m < 8; ++m) q[m] = ((sm >> m) & 1u) ? qv[m] : 0.f;
-            const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
-            float gl[4];
-            pignite_grad_tab(EdgeParams{J.p_h, J.a, J.c1, J.c2, J.c}, load_f4(J.rec, j),
-                             t8v[2 * j], t8v[2 * j + 1], sm, q, gl);
-            const float lj = lam[J.lam_off + j];
+        for (int e = 0; e < 4; ++e)
+            v[e] = (t[e] >= 1 && t[e] <= rings.T && attached(rings, t[e])) ? (uint32_t)t[e] : 0u;
+    } else {
 #pragma unroll
-            for (int m = 0; m < 4; ++m) g[m] += (double)(lj * gl[m]);
+        for (int e = 0; e < 4; ++e) v[e] = jq + e < cells ? (uint32_t)gmem(J.sm8)[jq + e] : 0u;
+    }
+    int tot;
+    int pos = block_exscan<4>((v[0] != 0u) + (v[1] != 0u) + (v[2] != 0u) + (v[3] != 0u), sWave,
+                              &tot);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        if (v[e]) {
+            sOff[pos] = (uint16_t)(4 * threadIdx.x + e);
+            sVal[pos] = v[e];
+            ++pos;
         }
     }
+    if (__builtin_amdgcn_readfirstlane(tot) == 0) {   // uniform: nothing listed
+        if (threadIdx.x < 4) gpart[(int64_t)b * 4 + threadIdx.x] = 0.0;
+        continue;
+    }
+    __syncthreads();
+    double g[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < tot; k += 256) {
+        const int64_t j = j0 + sOff[k];
+        const uint32_t val = sVal[k];
+        uint32_t sm;
+        if constexpr (FROM_MAPS) {
+            // burning neighbours at t_j - 1: ignited by then and not yet out
+            // (a grid holds at most 2^32 cells, so j fits 32 unsigned bits)
+            const int tj1 = (int)val - 1;
+            const uint32_t ju = (uint32_t)j, W = (uint32_t)J.W;
+            const int r = (int)(ju / W), c = (int)(ju - (uint32_t)r * W);
+            // (all 16 reads issued at once: a neighbour outside the grid
+            // reads cell j and is masked out)
+            const FS_GLOBAL int32_t* tg = gmem(J.tign);
+            const FS_GLOBAL int32_t* to = gmem(J.tout);
+            int ti[8], tu[8];
+            bool in[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                int dr, dc;
+                slot_dir(m, dr, dc);
+                const int rr = r + dr, cc = c + dc;
+                in[m] = rr >= 0 && rr < J.H && cc >= 0 && cc < J.W;
+                const int64_t i = in[m] ? (int64_t)rr * J.W + cc : j;
+                ti[m] = tg[i];
+                tu[m] = to[i];
+            }
+            sm = 0u;
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+                sm |= (uint32_t)(in[m] & (ti[m] <= tj1) & (tj1 < tu[m])) << m;
+        } else {
+            sm = val;
+        }
+        const float4 qa = load_f4(J.q8, 2 * j), qb = load_f4(J.q8, 2 * j + 1);
+        const FS_GLOBAL fs_f4* t8v = (const FS_GLOBAL fs_f4*)gmem(J.th8);
+        const fs_f4 ta = t8v[2 * j], tb = t8v[2 * j + 1];
+        const float4 rec = load_f4(J.rec, j);
+        const float lj = gmem(lam)[J.lam_off + j];
+        // (keeps the compiler from moving the lambda read down to its use,
+        // which would add a round trip after the arithmetic)
+        asm volatile("" ::: "memory");
+        const float qv[8] = {qa.x, qa.y, qa.z, qa.w, qb.x, qb.y, qb.z, qb.w};
+        float q[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) q[m] = ((sm >> m) & 1u) ? qv[m] : 0.f;
+        float gl[4];
+        pignite_grad_tab(EdgeParams{J.p_h, J.a, J.c1, J.c2, J.c}, rec, ta, tb, sm, q, gl);
+#pragma unroll
+        for (int m = 0; m < 4; ++m) g[m] += (double)(lj * gl[m]);
     }
     // wavefront sums by shuffles, then the 4 wavefronts in order
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-        double v = g[m];
+        double x = g[m];
 #pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) v += __shfl_down(v, d, 64);
-        if (lane == 0) sh[wv][m] = v;
+        for (int d = 32; d >= 1; d >>= 1) x += __shfl_down(x, d, 64);
+        if (lane == 0) sh[wv][m] = x;
     }
     __syncthreads();
     if (threadIdx.x < 4)
         gpart[(int64_t)b * 4 + threadIdx.x] =
             ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) + sh[3][threadIdx.x];
-    __syncthreads();   // sh is reused by the next segment
+    __syncthreads();   // sh and the list are reused by the next segment
     }
 }
 
