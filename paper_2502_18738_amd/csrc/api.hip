@@ -38,7 +38,10 @@ struct ScenLayout {
 
 struct Layout {
     size_t err, stats, box, part, jobs, tile_job, adj_jobs, adj_tile_job, sm8, lam,
-        cell0, bl0, ib0, gpart_tmap, masks, adj_masks, tielog, tie_n, fbox, qbox, cell0q, total;
+        cell0, bl0, ib0, gpart_tmap, masks, adj_masks, tielog, tie_n, fbox, qbox, cell0q, qbits,
+        total;
+    int64_t qwords, max_qwords;       // block bit words: all scenarios, largest scenario
+    std::vector<int64_t> qoff;        // first block bit word of each scenario
     int32_t mask_words, adj_mask_words;
     int64_t total_cells;
     int32_t tmap_blocks;
@@ -77,6 +80,17 @@ bool plan(const sim_desc* d, int n, uint32_t flags, int ckpt_every, int T_max, L
     L->fbox = take(16 * (size_t)n);                     // burning box at the table's origin step
     L->qbox = take(16 * (size_t)n);                     // table region per scenario
     L->cell0q = take(sizeof(int64_t) * (size_t)(n + 1));
+    // block bits of the table region (32 x 32-cell blocks, rows of
+    // cdiv(pitch, 32) words): burning blocks, row-grown, grown
+    L->qoff.assign(n + 1, 0);
+    L->max_qwords = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t w = cdiv(d[i].H, 32) * cdiv(cdiv(d[i].W, 32), 32);
+        L->qoff[i + 1] = L->qoff[i] + w;
+        L->max_qwords = std::max(L->max_qwords, w);
+    }
+    L->qwords = L->qoff[n];
+    L->qbits = take(3 * 4 * (size_t)L->qwords);
     L->total_cells = 0;
     for (int i = 0; i < n; ++i) L->total_cells += (int64_t)d[i].H * d[i].W;
     int64_t tiles = 0;
@@ -342,7 +356,8 @@ int refresh_worklist(sim_handle* h, bool dup) {
 int take_origin(sim_handle* h, int origin_step) {
     h->q_dirty = true;
     h->q_origin = origin_step;
-    return h->hip(fs::launch_bbox(h->st, h->d_jobs(), h->n, h->parity, h->max_words, h->d_fbox()),
+    return h->hip(fs::launch_bbox(h->st, h->d_jobs(), h->n, h->parity, h->max_words, h->d_fbox(),
+                                  reinterpret_cast<uint32_t*>(h->ws + h->L.qbits), h->L.qwords),
                   "burning box");
 }
 
@@ -496,6 +511,10 @@ int init_handle(sim_handle** out, const sim_desc* descs, int32_t n, void* worksp
         J.tout = h->calib() ? reinterpret_cast<int32_t*>(h->ws + s.tout) : nullptr;
         J.ckpt = h->calib() ? reinterpret_cast<uint32_t*>(h->ws + s.ckpt) : nullptr;
         J.sm8 = nullptr;   // set below with lam_off
+        uint32_t* qb = reinterpret_cast<uint32_t*>(h->ws + h->L.qbits);
+        J.qburn = qb + h->L.qoff[i];
+        J.qrow = qb + h->L.qwords + h->L.qoff[i];
+        J.qneed = qb + 2 * h->L.qwords + h->L.qoff[i];
         J.lam_off = 0;   // set below: offset of this scenario's grid in dL/dyhat
         h->max_words = std::max<int64_t>(h->max_words, s.PW);
     }
@@ -740,7 +759,7 @@ int ensure_qtable(sim_handle* h, int64_t t_end) {
     if (!h->q_dirty && t_end <= h->q_end) return SIM_OK;
     const int reach = (int)std::min<int64_t>(std::max<int64_t>(t_end - h->q_origin, 0), kMaxSide);
     int rc = h->hip(fs::launch_qtable(h->st, h->d_jobs(), h->d_fbox(), h->n, reach,
-                                      h->L.total_cells,
+                                      h->L.total_cells, h->L.max_qwords,
                                       reinterpret_cast<int4*>(h->ws + h->L.qbox),
                                       reinterpret_cast<int64_t*>(h->ws + h->L.cell0q)),
                     "propagation table");

@@ -51,6 +51,14 @@ struct DevScen {
                                // step, recorded by the checkpoint adjoint's recompute
                                // (0: none); nullptr outside calibration
     int64_t lam_off;           // offset of this scenario's dL/dyhat grid
+    // Blocks of 32 x 32 cells (block (br, bc): rows 32 br .. 32 br + 31, word
+    // bc of each row), one bit each, rows of cdiv(pitch, 32) words: blocks
+    // with a burning cell at the propagation table's origin step, the same
+    // grown along the rows, and grown along the columns too (the blocks the
+    // table covers)
+    uint32_t* qburn;
+    uint32_t* qrow;
+    uint32_t* qneed;
     void* tielog;              // near-tie records (sim_tie layout) or nullptr
     unsigned long long* tie_n; // number of trials logged
 };
@@ -119,15 +127,24 @@ hipError_t launch_arrival(hipStream_t st, const DevScen* d_jobs, const DevScen& 
 hipError_t launch_overlap(hipStream_t st, const DevScen& job, int32_t parity, const uint8_t* target,
                           long long* out);
 // box[s] = (r0, r1, c0, c1), the bounding box of the burning cells of every
-// scenario in planes[parity] (r1 < r0: nothing burns).
+// scenario in planes[parity] (r1 < r0: nothing burns), and the qburn bits of
+// the 32 x 32 blocks holding a burning cell; qburn_all (qwords words) is the
+// bit array of all scenarios, cleared first.
 hipError_t launch_bbox(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
-                       int64_t max_words, int4* box);
+                       int64_t max_words, int4* box, uint32_t* qburn_all, int64_t qwords);
+// Largest reach (in blocks of 32 cells) for which the table is restricted to
+// the blocks near a burning block (qneed); beyond it the box alone bounds it.
+constexpr int kMaxBlockReach = 16;
 // Propagation table q8 of every scenario for the current parameters, over the
 // cells within `reach` of box[s] (the only cells that can have an ignition
-// trial in the next `reach` steps); qbox (n) and cell0q (n + 1) are scratch
-// for the regions and their prefix sums; max_cells bounds their total.
+// trial in the next `reach` steps) and, when ceil(reach / 32) <=
+// kMaxBlockReach, in the blocks within ceil(reach / 32) blocks of a qburn
+// block; qbox (n) and cell0q (n + 1) are scratch for the regions and their
+// prefix sums; max_cells bounds their total, max_qwords the bit words of a
+// scenario.
 hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int4* box, int32_t n,
-                         int32_t reach, int64_t max_cells, int4* qbox, int64_t* cell0q);
+                         int32_t reach, int64_t max_cells, int64_t max_qwords, int4* qbox,
+                         int64_t* cell0q);
 // State of every scenario back to its initial burning cells (both ping-pong
 // buffers; with maps, also the accumulator and time maps); d_ib0 = n + 1
 // prefix sums of the blocks per scenario, ceil(H * pitch / 256).

@@ -948,9 +948,11 @@ k_slopes(DevScen J, float* __restrict__ th8, const float* __restrict__ slope9,
 // Bounding box (r0, r1, c0, c1) of the burning cells of every scenario in
 // planes[parity] (r1 < r0 when nothing burns): the fire can only reach cells
 // within t steps of it t steps later (one Moore neighbour per step).
-__global__ void k_bbox_clear(int4* __restrict__ box, int32_t n) {
+__global__ void k_bbox_clear(int4* __restrict__ box, int32_t n, uint32_t* __restrict__ qburn,
+                             int64_t qwords) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) box[i] = make_int4(INT_MAX, -1, INT_MAX, -1);
+    for (int64_t w = i; w < qwords; w += (int64_t)gridDim.x * 256) qburn[w] = 0u;
 }
 
 __global__ void __launch_bounds__(256)
@@ -959,6 +961,8 @@ k_bbox(const DevScen* __restrict__ jobs, int32_t parity, int4* __restrict__ box)
     const int64_t PW = (int64_t)J.H * J.pitch;
     const FS_GLOBAL uint32_t* B = gmem(J.planes[parity]);
     int r0 = INT_MAX, r1 = -1, c0 = INT_MAX, c1 = -1;
+    FS_GLOBAL uint32_t* qb = gmem(J.qburn);
+    const int nbw = (J.pitch + 31) >> 5;
     auto word = [&](int64_t o, uint32_t w) {
         if (w) {
             const int r = (int)(o / J.pitch), cw = (int)(o - (int64_t)r * J.pitch);
@@ -966,6 +970,10 @@ k_bbox(const DevScen* __restrict__ jobs, int32_t parity, int4* __restrict__ box)
             r1 = max(r1, r);
             c0 = min(c0, 32 * cw + __builtin_ctz(w));
             c1 = max(c1, 32 * cw + 31 - __builtin_clz(w));
+            // block (r / 32, cw): set its bit unless already seen set
+            const int64_t bw = (int64_t)(r >> 5) * nbw + (cw >> 5);
+            const uint32_t bit = 1u << (cw & 31);
+            if (!(qb[bw] & bit)) atomicOr(J.qburn + bw, bit);
         }
     };
     // 4 words (16 bytes) per lane; the plane starts 256-byte aligned
@@ -995,6 +1003,42 @@ k_bbox(const DevScen* __restrict__ jobs, int32_t parity, int4* __restrict__ box)
         atomicMax(&b[1], r1);
         atomicMin(&b[2], c0);
         atomicMax(&b[3], c1);
+    }
+}
+
+// Blocks within R blocks (Chebyshev) of a qburn block, in two passes: ROWS
+// writes qrow, each bit the OR of the qburn bits R blocks to either side in
+// its row; the column pass writes qneed, the OR of the qrow bits R block rows
+// above and below.  A cell within `reach` cells of a burning cell lies in a
+// block within ceil(reach / 32) blocks of that cell's block.  One thread per
+// output word; a grid row (blockIdx.y) per scenario.
+template <bool ROWS>
+__global__ void __launch_bounds__(256)
+k_qdilate(const DevScen* __restrict__ jobs, int32_t R) {
+    const DevScen& J = jobs[blockIdx.y];
+    const int nbr = (J.H + 31) >> 5, nbw = (J.pitch + 31) >> 5;
+    const int64_t words = (int64_t)nbr * nbw;
+    const FS_GLOBAL uint32_t* in = gmem(ROWS ? J.qburn : J.qrow);
+    FS_GLOBAL uint32_t* out = gmem(ROWS ? J.qrow : J.qneed);
+    for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < words;
+         o += (int64_t)gridDim.x * 256) {
+        const int br = (int)(o / nbw), k = (int)(o - (int64_t)br * nbw);
+        uint32_t acc = 0u;
+        if constexpr (ROWS) {
+            // bits 32 k + s .. 32 k + s + 31 of the row, zero outside it
+            const FS_GLOBAL uint32_t* row = in + (int64_t)br * nbw;
+            auto at = [&](int w) -> uint32_t { return (w >= 0 && w < nbw) ? row[w] : 0u; };
+            for (int s = -R; s <= R; ++s) {
+                const int p = 32 * k + s;
+                const int w = p >> 5, sh = p & 31;   // (p >> 5 rounds down for p < 0)
+                const uint32_t lo = at(w);
+                acc |= sh ? (lo >> sh) | (at(w + 1) << (32 - sh)) : lo;
+            }
+        } else {
+            for (int a = max(0, br - R); a <= min(nbr - 1, br + R); ++a)
+                acc |= in[(int64_t)a * nbw + k];
+        }
+        out[o] = acc;
     }
 }
 
@@ -1047,7 +1091,7 @@ k_qbox(const DevScen* __restrict__ jobs, const int4* __restrict__ box, int32_t n
 // the region sizes.  A fixed grid walks the 256-cell segments.
 __global__ void __launch_bounds__(256)
 k_qtable(const DevScen* __restrict__ jobs, const int4* __restrict__ qbox,
-         const int64_t* __restrict__ cell0, int32_t n) {
+         const int64_t* __restrict__ cell0, int32_t n, int32_t masked) {
     // one cell: q8 of its 8 incoming edges
     auto cell = [&](const DevScen& J, int64_t j) {
         const float4 rec = load_f4(J.rec, j);
@@ -1064,12 +1108,20 @@ k_qtable(const DevScen* __restrict__ jobs, const int4* __restrict__ qbox,
         o[0] = fs_f4{q[0], q[1], q[2], q[3]};
         o[1] = fs_f4{q[4], q[5], q[6], q[7]};
     };
-    // region index i of scenario s -> grid cell
-    // (a region holds at most 65 536^2 cells, so i fits 32 unsigned bits)
+    // region index i of scenario s -> its cell, if that cell's block is one
+    // the table covers (a region holds at most 65 536^2 cells, so i fits 32
+    // unsigned bits)
     auto at = [&](int s, int64_t i) {
         const int4 q = qbox[s];
         const uint32_t ii = (uint32_t)i, rr = ii / (uint32_t)q.z;
-        return (int64_t)(q.x + (int)rr) * jobs[s].W + (q.y + (int)(ii - rr * (uint32_t)q.z));
+        const int r = q.x + (int)rr, c = q.y + (int)(ii - rr * (uint32_t)q.z);
+        const DevScen& J = jobs[s];
+        if (masked) {
+            const int nbw = (J.pitch + 31) >> 5;
+            const uint32_t w = gmem(J.qneed)[(int64_t)(r >> 5) * nbw + (c >> 10)];
+            if (!((w >> ((c >> 5) & 31)) & 1u)) return (int64_t)-1;
+        }
+        return (int64_t)r * J.W + c;
     };
     const int64_t total = cell0[n];
     const int64_t nvb = (total + 255) / 256;
@@ -1089,11 +1141,13 @@ k_qtable(const DevScen* __restrict__ jobs, const int4* __restrict__ qbox,
         if (g0 + 256 <= cell0[lo + 1]) {
             // the whole segment lies in scenario lo: its descriptor is uniform
             const int su = __builtin_amdgcn_readfirstlane(lo);
-            cell(jobs[su], at(su, gi - cell0[su]));
+            const int64_t j = at(su, gi - cell0[su]);
+            if (j >= 0) cell(jobs[su], j);
         } else if (gi < total) {
             int s = lo;   // the segment straddles scenarios
             while (gi >= cell0[s + 1]) ++s;
-            cell(jobs[s], at(s, gi - cell0[s]));
+            const int64_t j = at(s, gi - cell0[s]);
+            if (j >= 0) cell(jobs[s], j);
         }
     }
 }
@@ -2071,23 +2125,33 @@ hipError_t launch_arrival(hipStream_t st, const DevScen* d_jobs, const DevScen& 
 }
 
 hipError_t launch_bbox(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
-                       int64_t max_words, int4* box) {
+                       int64_t max_words, int4* box, uint32_t* qburn_all, int64_t qwords) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bbox_clear, dim3((n + 255) / 256), dim3(256), 0, st, box, n);
+    const int64_t gc = std::max<int64_t>((n + 255) / 256, std::min<int64_t>((qwords + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_bbox_clear, dim3((unsigned)gc), dim3(256), 0, st, box, n, qburn_all,
+                       qwords);
     const unsigned gx = (unsigned)std::min<int64_t>((max_words + 1023) / 1024, 64);
     hipLaunchKernelGGL(k_bbox, dim3(gx, n), dim3(256), 0, st, d_jobs, parity, box);
     return hipGetLastError();
 }
 
 hipError_t launch_qtable(hipStream_t st, const DevScen* d_jobs, const int4* box, int32_t n,
-                         int32_t reach, int64_t max_cells, int4* qbox, int64_t* cell0q) {
+                         int32_t reach, int64_t max_cells, int64_t max_qwords, int4* qbox,
+                         int64_t* cell0q) {
     if (n <= 0) return hipSuccess;
+    const int R = (reach + 31) / 32;
+    const bool masked = R <= kMaxBlockReach;
+    if (masked) {
+        const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_qwords + 255) / 256, 64));
+        hipLaunchKernelGGL(k_qdilate<true>, dim3(gx, n), dim3(256), 0, st, d_jobs, R);
+        hipLaunchKernelGGL(k_qdilate<false>, dim3(gx, n), dim3(256), 0, st, d_jobs, R);
+    }
     hipLaunchKernelGGL(k_qbox, dim3(1), dim3(256), 0, st, d_jobs, box, n, reach, qbox, cell0q);
     // the region sizes are known on the device only: a grid that covers the
     // largest possible total walks what is there
     const int64_t nvb = (max_cells + 255) / 256;
     hipLaunchKernelGGL(k_qtable, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(nvb, 8192))),
-                       dim3(256), 0, st, d_jobs, qbox, cell0q, n);
+                       dim3(256), 0, st, d_jobs, qbox, cell0q, n, masked ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -1114,6 +1114,39 @@ def test_table_region_follows_the_state(Sim):
     check_light_cone(gstate(sim), st2, ties2, 25)
 
 
+def test_table_blocks_around_distant_fires(Sim):
+    """Fires in opposite corners of a grid many 32 x 32 blocks wide: the table
+    covers the blocks within reach of each fire, not the box between them.
+    Split runs (the table grows with the steps) and spotting in a block far
+    from both fires follow the oracle."""
+    s = synth.make_plain(420, 600, 83, ignitions=[(6, 10), (410, 585), (200, 40)], T=70)
+    states, ties = oracle_traj(s, 70)
+    split = Sim([s])
+    done = 0
+    for k in (3, 9, 20, 38):   # reach 3 .. 70 cells: 1 .. 3 blocks
+        split.run(k)
+        done += k
+        check_light_cone(gstate(split), states, ties, done)
+    whole = Sim([s])
+    whole.run(70)
+    assert np.array_equal(whole.get_state(0).cpu().numpy(), split.get_state(0).cpu().numpy())
+    # spotting in the middle of the grid, far from every burning block
+    sim = Sim([s])
+    sim.run(12)
+    S12 = states[12]
+    spot = np.array([210 * s.W + 300, 30 * s.W + 400])
+    sim.ignite(0, spot)
+    patched = S12.copy().ravel()
+    patched[spot] = np.where(patched[spot] == 2, 2, 1)
+    patched = patched.reshape(S12.shape)
+    st2, ties2 = oracle_traj(s, 40, S0=patched, t0=12)
+    sim.run(40)
+    bad = check_light_cone(gstate(sim), st2, ties2, 40)
+    say("distant fires: cells in near-tie cones", bad)
+    # the spotted fires did spread
+    assert (gstate(sim)[200:221, 290:311] != 0).sum() > 20
+
+
 # ------------------------------------------------------------ degenerate cases
 
 def degenerate_cases():
