@@ -198,9 +198,10 @@ SIM_API int sim_get_exec(const sim_handle* h, sim_exec* e);
  * cells at the origin step (the last reset, set_state or ignite). */
 SIM_API int sim_prepare(sim_handle* h, int32_t T);
 
-/* Autotuner: times every compiled execution shape (temporal depth = the
- * shape's halo, skipping on) over T_probe steps from the current state, keeps
- * the fastest and writes it to *best (nullable).  The state and step counter
+/* Autotuner: times every compiled execution shape (skipping on; temporal
+ * depth: T_probe steps in as few launches as the shape's halo allows, spread
+ * evenly, e.g. 10 for 20 steps on a 16-step halo) over T_probe steps from the
+ * current state, keeps the fastest and writes it to *best (nullable).  The state and step counter
  * are restored afterwards, so results do not depend on having tuned.  Waits
  * for the stream.  Not available in calibration mode (SIM_E_STATE). */
 SIM_API int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best);

@@ -897,8 +897,17 @@ int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best) {
     float best_ms = 1e30f;
     sim_exec best_ex = ex0;
     for (int c = 0; c < 2 * ns && !rc; ++c) {
-        const sim_exec ex{shapes[c % ns].tr, shapes[c % ns].tc, shapes[c % ns].km, 1 + c / ns,
-                          shapes[c % ns].nt};
+        // the probe's steps in as few launches as the halo allows, spread
+        // evenly over them (20 steps on a 16-step halo: two launches of 10,
+        // whose cells need 10 halo rows, not 16)
+        const int km = shapes[c % ns].km;
+        const int launches = (T_probe + km - 1) / km;
+        sim_exec ex{shapes[c % ns].tr, shapes[c % ns].tc,
+                    std::min(km, (T_probe + launches - 1) / launches), 1 + c / ns,
+                    shapes[c % ns].nt};
+        // (a depth that maps to a smaller halo would select another, possibly
+        // uncompiled shape: such short probes keep the shape's own halo)
+        if (shape_of(ex).km != km) ex.depth = km;
         rc = sim_set_exec(h, &ex);
         if (!rc) rc = restore();
         if (!rc) rc = enqueue_run(h, h->st, T_probe, nullptr);   // warm-up
