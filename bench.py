@@ -138,11 +138,13 @@ def timed(fn, steps, warmup, torch):
 
 def step_kernel_name(ex):
     """The forward step instantiation of an execution shape (the last template
-    argument: worklist launches, skip mode 1)."""
+    argument, the work-item mode: 0 every tile (skip modes 0 and 2), 1 the
+    worklist (skip mode 1), 2 every tile tested against the worklist (skip
+    mode 3))."""
     return "k_step<{},{},{},false,{},{}>".format(
         ex["tile_rows"], ex["tile_words"], km_bucket(ex["depth"]),
         ex.get("threads") or (512 if ex["tile_rows"] >= 32 else 256),
-        "true" if int(ex["skip"]) == 1 else "false")
+        {1: 1, 3: 2}.get(int(ex["skip"]), 0))
 
 
 def work_counts(Sim, scs, ex, T, torch):
@@ -455,7 +457,7 @@ def main():
     ap.add_argument("--legs", default="main,plain,calib,batched,paper,cpu")
     ap.add_argument("--exec", default=None, metavar="TR,TC,DEPTH,SKIP[,THREADS]",
                     help="execution shape of the main leg (tile rows, tile words, steps "
-                         "per launch, skip 0/1/2, work-group size or 0 for the default)")
+                         "per launch, skip 0/1/2/3, work-group size or 0 for the default)")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the main leg's shape on a mid-run state (the batched "
                          "leg always autotunes)")

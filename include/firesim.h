@@ -132,7 +132,9 @@ typedef struct {
  * tiles with no burning cell within reach are skipped: 0 = every tile is
  * processed, 1 = a device-built worklist (tiles that burn mark their
  * neighbours for the next launch; a grid of resident work-groups walks it),
- * 2 = every tile is launched and tests its neighbours' flags.  threads is the
+ * 2 = every tile is launched and tests its neighbours' flags, 3 = every tile
+ * is launched and tests its bit of the worklist (one read; mode 1's lists,
+ * mode 2's launch shape and register budget).  threads is the
  * work-group size (0 = the shape's default: 256 lanes for tiles of up to 16
  * rows, 512 for 32-row tiles, which are also compiled with 256).  Every shape
  * produces bit-identical states. */

@@ -695,7 +695,7 @@ int sim_set_exec(sim_handle* h, const sim_exec* e) {
         (h->calib() && !fs::step_shape_supported(sh, true)))
         return h->fail(SIM_E_SHAPE, "tile %dx%d words with depth %d (%d threads) is not compiled in",
                        e->tile_rows, e->tile_words, e->depth, e->threads);
-    if (e->skip < 0 || e->skip > 2) return h->fail(SIM_E_ARG, "skip must be 0, 1 or 2");
+    if (e->skip < 0 || e->skip > 3) return h->fail(SIM_E_ARG, "skip must be 0, 1, 2 or 3");
     h->ex = *e;
     const bool same = sh.tr == h->sh.tr && sh.tc == h->sh.tc;
     h->sh = sh;
@@ -719,7 +719,7 @@ int enqueue_run(sim_handle* h, hipStream_t st, int T, unsigned long long* stats)
         int k = std::min(h->ex.depth, T);
         if (h->calib()) k = std::min(k, h->ckpt_every - h->step % h->ckpt_every);
         fs::Sched sc{nullptr, nullptr, nullptr, h->L.mask_words};
-        if (h->ex.skip == 1) {
+        if (h->ex.skip == 1 || h->ex.skip == 3) {
             unsigned long long* m = h->d_masks();
             const int64_t nw = h->L.mask_words;
             sc.in = m + nw * (h->lidx % 3);
@@ -896,7 +896,7 @@ int sim_autotune(sim_handle* h, int32_t T_probe, sim_exec* best) {
     h->use_graphs = false;
     float best_ms = 1e30f;
     sim_exec best_ex = ex0;
-    for (int c = 0; c < 2 * ns && !rc; ++c) {
+    for (int c = 0; c < 3 * ns && !rc; ++c) {
         // the probe's steps in as few launches as the halo allows, spread
         // evenly over them (20 steps on a 16-step halo: two launches of 10,
         // whose cells need 10 halo rows, not 16)
@@ -1134,7 +1134,7 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
                                                h->sh), "adjoint flags");
     auto* amask = reinterpret_cast<unsigned long long*>(h->ws + h->L.adj_masks);
     const int64_t anw = h->L.adj_mask_words;
-    if (!rc && h->ex.skip == 1)
+    if (!rc && (h->ex.skip == 1 || h->ex.skip == 3))
         rc = h->hip(fs::launch_mask_init(h->st, d_adj, d_adj_tiles, h->adj_ntiles, 0, amask,
                                          h->L.adj_mask_words), "adjoint worklist");
     int alidx = 0;
@@ -1148,7 +1148,7 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
     for (int off = 0; off < h->ckpt_every && !rc; ) {
         const int k = std::min(h->ex.depth, h->ckpt_every - off);
         fs::Sched sc{nullptr, nullptr, nullptr, h->L.adj_mask_words};
-        if (h->ex.skip == 1) {
+        if (h->ex.skip == 1 || h->ex.skip == 3) {
             sc.in = amask + anw * (alidx % 3);
             sc.out = amask + anw * ((alidx + 1) % 3);
             sc.clear = amask + anw * ((alidx + 2) % 3);

@@ -283,6 +283,13 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 
 // --------------------------------------------------------------- main step
 
+// Work items of a step launch: every tile (skip modes 0 and 2: all, or those
+// whose neighbourhood's flags show fire), the tiles of the previous launch's
+// worklist walked by a resident grid (mode 1), or every tile launched and
+// tested against that worklist (mode 3: one read decides, before anything
+// that depends on the tile's job).  Each is compiled separately.
+constexpr int kAllTiles = 0, kWorklist = 1, kAllTilesListed = 2;
+
 // 256-lane shapes serve many busy tiles at once (ensembles, calibration): they
 // keep no per-word slot masks in LDS (see SN below), so that more work-groups
 // fit a CU, and they aim at a register budget per wavefront: 64 registers (8
@@ -292,22 +299,24 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
 // (measured: the tighter targets gain 2-4 % on calibration and the ensemble).
 // Where a shape cannot reach its target the compiler settles on the occupancy
 // it can reach (its warning is silenced).
-template <int TR, int TC, int KM, bool ADJ, int NT, bool LISTED>
+template <int TR, int TC, int KM, bool ADJ, int NT, int MODE>
 constexpr int step_waves() {
     constexpr int wpt = ((TR + 2 * KM) * (TC + 2) + NT - 1) / NT;
-    return NT >= 512 ? 1 : LISTED ? 5 : (wpt <= 2 ? 8 : 7);
+    return NT >= 512 ? 1 : MODE == kWorklist ? 5 : (wpt <= 2 ? 8 : 7);
 }
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Wpass-failed"
-template <int TR, int TC, int KM, bool ADJ, int NT, bool LISTED>
+template <int TR, int TC, int KM, bool ADJ, int NT, int MODE>
 __global__ void __launch_bounds__(NT)
-    __attribute__((amdgpu_waves_per_eu(step_waves<TR, TC, KM, ADJ, NT, LISTED>())))
+    __attribute__((amdgpu_waves_per_eu(step_waves<TR, TC, KM, ADJ, NT, MODE>())))
 k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, int32_t ntiles,
        int32_t parity, int32_t t_off, int32_t ksteps, int32_t skip,
        const float* __restrict__ lam, Rings rings, Sched sched,
        unsigned long long* __restrict__ stats) {
     constexpr int RR = TR + 2 * KM, RC = TC + 2, NW = RR * RC;
     constexpr int WPT = (NW + NT - 1) / NT;
+    constexpr bool LISTED = MODE == kWorklist;
+    constexpr bool WLTEST = MODE == kAllTilesListed;
     constexpr int NWAVE = NT / 64;
     constexpr int LCAP = NW * 32;  // worst case: every cell of the region has a trial
     static_assert(LCAP <= 32768, "entries carry an ignition flag in bit 15");
@@ -349,8 +358,8 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
 
     // ---- work items: every tile (one per work-group), or the tiles the
     // previous launch marked (worklist: a fixed grid walks the set bits).
-    // The two are compiled separately, so that launches over every tile carry
-    // none of the worklist's registers.
+    // The modes are compiled separately, so that launches over every tile
+    // carry none of the worklist walk's registers.
     __shared__ int sItems, sTile;
     constexpr bool listed = LISTED;
     const FS_GLOBAL unsigned long long* sin = gmem(sched.in);
@@ -366,6 +375,10 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         for (int w = blockIdx.x * NT + tid; w < sched.nwords; w += gridDim.x * NT)
             gmem(sched.clear)[w] = 0ull;
         __syncthreads();
+    } else if (WLTEST) {
+        // every tile launched, the worklist consulted: the same hand-over
+        for (int w = blockIdx.x * NT + tid; w < sched.nwords; w += gridDim.x * NT)
+            gmem(sched.clear)[w] = 0ull;
     }
     const int nitems = listed ? sItems : 1;
     for (int it = listed ? blockIdx.x : 0; it < nitems; it += listed ? gridDim.x : 1) {
@@ -390,6 +403,10 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
     } else {
         g = xcd_tile(blockIdx.x, gridDim.x);
         if (g >= ntiles) continue;
+        // skip mode 3: a tile the previous launch did not list has no fire
+        // within reach and two equal buffers; the test reads one word, before
+        // anything that depends on the tile's job
+        if (WLTEST && !((sin[g >> 6] >> (g & 63)) & 1ull)) continue;
     }
     // (launches over every tile of a single job pass no tile -> job table)
     const DevScen& J = jobs[(!LISTED && !tile_job) ? 0 : tile_job[g]];
@@ -410,7 +427,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
 
     // ---- skip a tile when no tile within reach holds a burning cell
     bool need = true;
-    if (skip) {
+    if (!WLTEST && skip) {
         need = false;
         for (int dr = -1; dr <= 1; ++dr)
             for (int dc = -1; dc <= 1; ++dc) {
@@ -888,7 +905,7 @@ k_step(const DevScen* __restrict__ jobs, const int32_t* __restrict__ tile_job, i
         }
         if (tid == 0) atomicAdd(&stats[0], 1ull);
     }
-    if (listed && tid < 9) {
+    if ((listed || WLTEST) && tid < 9) {
         // mark the next launch's work: the 3 x 3 tile neighbourhood while the
         // tile burns, the tile alone when it changed (its two buffers differ)
         const int f = sFlag;
@@ -2274,14 +2291,17 @@ struct StepEntry {
     bool adj;
     StepFn fn;        // every tile (skip modes 0 and 2)
     StepFn fn_list;   // the tiles of a worklist (skip mode 1)
+    StepFn fn_wl;     // every tile, tested against a worklist (skip mode 3)
     int resident;     // work-groups of fn_list resident at once (0: not queried yet)
 };
 
 #define FS_SHAPE_NT(TR, TC, KM, NT)                                                      \
-    {TR, TC, KM, NT, false, &k_step<TR, TC, KM, false, NT, false>,                         \
-     &k_step<TR, TC, KM, false, NT, true>, 0},                                             \
-    {TR, TC, KM, NT, true, &k_step<TR, TC, KM, true, NT, false>,                           \
-     &k_step<TR, TC, KM, true, NT, true>, 0},
+    {TR, TC, KM, NT, false, &k_step<TR, TC, KM, false, NT, kAllTiles>,                     \
+     &k_step<TR, TC, KM, false, NT, kWorklist>,                                            \
+     &k_step<TR, TC, KM, false, NT, kAllTilesListed>, 0},                                  \
+    {TR, TC, KM, NT, true, &k_step<TR, TC, KM, true, NT, kAllTiles>,                       \
+     &k_step<TR, TC, KM, true, NT, kWorklist>,                                             \
+     &k_step<TR, TC, KM, true, NT, kAllTilesListed>, 0},
 // 32-row tiles come with both sizes (the default first): 512 lanes shorten
 // the per-step latency of a few busy tiles, 256 lanes give more resident
 // work-groups when many tiles are busy at once (large ensembles).
@@ -2339,7 +2359,8 @@ hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_
     if (!e || ksteps > sh.km) return hipErrorInvalidValue;
     if (ntiles <= 0) return hipSuccess;
     int nb = ntiles;
-    if (sched.in) {
+    const bool listed = sched.in && skip == 1;
+    if (listed) {
         // as many work-groups as can be resident at once (occupancy x CUs),
         // capped by the caller and by the tile count
         if (e->resident == 0) {
@@ -2355,8 +2376,9 @@ hipError_t launch_step(hipStream_t st, TileShape sh, bool adj, const DevScen* d_
         }
         nb = std::max(1, std::min(std::min(grid, e->resident), ntiles));
     }
-    hipLaunchKernelGGL(sched.in ? e->fn_list : e->fn, dim3(nb), dim3(e->nt), 0, st, d_jobs,
-                       d_tile_job, ntiles, parity, t_off, ksteps, sched.in ? 0 : skip, lam,
+    hipLaunchKernelGGL(listed ? e->fn_list : (skip == 3 ? e->fn_wl : e->fn), dim3(nb),
+                       dim3(e->nt), 0, st, d_jobs,
+                       d_tile_job, ntiles, parity, t_off, ksteps, listed ? 0 : skip, lam,
                        rings, sched, d_stats);
     return hipGetLastError();
 }

@@ -162,8 +162,9 @@ class Sim:
 
     # --------------------------------------------------------------- calls
     def set_exec(self, tile_rows=32, tile_words=2, depth=32, skip=1, threads=0):
-        """skip: 0 process every tile, 1 (or True) device worklist, 2 per-tile test;
-        threads: work-group size (0 = the shape's default)."""
+        """skip: 0 process every tile, 1 (or True) device worklist, 2 per-tile test
+        of the neighbours' flags, 3 every tile launched and tested against the
+        worklist; threads: work-group size (0 = the shape's default)."""
         e = _abi.sim_exec(int(tile_rows), int(tile_words), int(depth), int(skip), int(threads))
         with self._on_stream():
             self._check(self._lib.sim_set_exec(self._h, ctypes.byref(e)))

@@ -147,6 +147,8 @@ SHAPES = [
     dict(tile_rows=32, tile_words=1, depth=16, skip=1),
     dict(tile_rows=32, tile_words=2, depth=32, skip=1),
     dict(tile_rows=32, tile_words=4, depth=20, skip=2),
+    dict(tile_rows=32, tile_words=8, depth=10, skip=3),
+    dict(tile_rows=16, tile_words=4, depth=1, skip=3),
     dict(tile_rows=32, tile_words=4, depth=8, skip=1, threads=256),
     dict(tile_rows=32, tile_words=2, depth=32, skip=0, threads=512),
     dict(tile_rows=32, tile_words=2, depth=32, skip=1, threads=256),
@@ -177,6 +179,7 @@ CHUNK_SHAPES = [
     dict(tile_rows=16, tile_words=8, depth=8, skip=0),
     dict(tile_rows=16, tile_words=4, depth=4, skip=1),
     dict(tile_rows=32, tile_words=2, depth=32, skip=1, threads=256),
+    dict(tile_rows=32, tile_words=4, depth=8, skip=3, threads=256),
 ]
 
 
@@ -461,7 +464,7 @@ def config4_oracle(b):
 
 
 @pytest.mark.parametrize("shape", ["tuned", "32x4d8s2t256", "32x4d8s1t256", "32x4d8s0t256",
-                                   "32x2d32s1t512"])
+                                   "32x8d10s3t256", "32x2d32s1t512"])
 @pytest.mark.parametrize("method", ["checkpoint", "timemap"])
 def test_config4_full_size_gradient(Sim, shape, method):
     """Calibration at full size: two of the 64 scenarios (1024 x 1024, 200
@@ -513,6 +516,7 @@ GRAD_SHAPES = {
     "32x4d8s2t256": dict(tile_rows=32, tile_words=4, depth=8, skip=2, threads=256),
     "32x4d8s1t256": dict(tile_rows=32, tile_words=4, depth=8, skip=1, threads=256),
     "32x4d8s0t256": dict(tile_rows=32, tile_words=4, depth=8, skip=0, threads=256),
+    "32x8d10s3t256": dict(tile_rows=32, tile_words=8, depth=10, skip=3, threads=256),
     "32x2d16s2t256": dict(tile_rows=32, tile_words=2, depth=16, skip=2, threads=256),
     "16x4d8s1": dict(tile_rows=16, tile_words=4, depth=8, skip=1),
 }
