@@ -193,8 +193,10 @@ SIM_API int sim_get_exec(const sim_handle* h, sim_exec* e);
 
 /* Build the per-edge propagation table (Eq. 2-5 for every edge the fire can
  * reach in the next T steps) now.  sim_run builds it itself when needed
- * (after sim_reset, sim_set_params, sim_set_wind, sim_set_state, sim_ignite,
- * or when a run goes past the steps it was built for); calling sim_prepare
+ * (after sim_set_params, sim_set_wind, sim_set_state, sim_ignite, after
+ * sim_reset unless the table was last built around the reset state under the
+ * current parameters and wind, or when a run goes past the steps it was built
+ * for); calling sim_prepare
  * first keeps that work out of a timed region or a captured launch sequence.
  * The table covers the cells within (step + T - origin) cells of the burning
  * cells at the origin step (the last reset, set_state or ignite). */
@@ -233,7 +235,10 @@ SIM_API int sim_set_params(sim_handle* h, const sim_params* per_scenario);
 
 /* Restore every scenario to init_burning at step 0 and clear the
  * accumulator (Algorithm 1, model.reset).  `seeds` (host, n entries) replaces
- * the Philox keys, or is NULL to keep them. */
+ * the Philox keys, or is NULL to keep them.  A propagation table built around
+ * the reset state under the current parameters and wind stays valid (it does
+ * not depend on the seeds), so runs of an ensemble that only changes seeds
+ * do not rebuild it. */
 SIM_API int sim_reset(sim_handle* h, const uint64_t* seeds);
 
 /* Copy scenario s's state into `out` (device, 2*H*W bytes: channel 0 =

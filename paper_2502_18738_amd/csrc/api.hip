@@ -252,6 +252,10 @@ struct sim_handle {
     // The table covers the cells within (q_end - q_origin) of the burning box
     // taken at step q_origin: every ignition trial up to step q_end.
     int q_origin = 0, q_end = 0;
+    // q_params: the parameters or the wind changed since the table was last
+    // built; q_reset: the table's origin is the reset state (the same burning
+    // cells after every reset), so a reset may keep a table built from it
+    bool q_params = true, q_reset = false;
     // calibration mode: the parameters changed after the run started, so the
     // checkpoints / time maps no longer match the parameters an adjoint would
     // differentiate; cleared by sim_reset
@@ -352,9 +356,13 @@ int refresh_worklist(sim_handle* h, bool dup) {
 }
 
 // The state changed other than by stepping (reset, set_state, spotting):
-// the propagation table is rebuilt around the new burning box.
-int take_origin(sim_handle* h, int origin_step) {
-    h->q_dirty = true;
+// the propagation table is rebuilt around the new burning box, unless this is
+// a reset and the table was built around the reset state under the current
+// parameters and wind (every reset starts from the same burning cells, so
+// the region and every entry are those it would rebuild).
+int take_origin(sim_handle* h, int origin_step, bool reset) {
+    if (!(reset && h->q_reset && !h->q_params && !h->q_dirty)) h->q_dirty = true;
+    h->q_reset = reset;
     h->q_origin = origin_step;
     return h->hip(fs::launch_bbox(h->st, h->d_jobs(), h->n, h->parity, h->max_words, h->d_fbox(),
                                   reinterpret_cast<uint32_t*>(h->ws + h->L.qbits), h->L.qwords),
@@ -369,7 +377,8 @@ int save_ckpt(sim_handle* h, int slot) {
 int reset_state(sim_handle* h) {
     h->parity = 0;
     h->step = 0;
-    // every run from a reset rebuilds the propagation table (take_origin)
+    // the propagation table is rebuilt unless the last one was built around
+    // the reset state with the current parameters and wind (take_origin)
     int rc = h->hip(fs::launch_init_state(h->st, h->d_jobs(),
                                           reinterpret_cast<const int32_t*>(h->ws + h->L.ib0),
                                           h->n, h->ib0.back(),
@@ -377,7 +386,7 @@ int reset_state(sim_handle* h) {
                                           h->L.total_cells, h->calib()), "init state");
     if (rc) return rc;
     rc = refresh_worklist(h, false);   // init_state wrote both buffers
-    if (!rc) rc = take_origin(h, 0);
+    if (!rc) rc = take_origin(h, 0, true);
     if (rc) return rc;
     rc = h->hip(hipMemsetAsync(h->d_stats(), 0, 4 * sizeof(unsigned long long), h->st),
                 "clear stats");
@@ -764,7 +773,7 @@ int ensure_qtable(sim_handle* h, int64_t t_end) {
                                       reinterpret_cast<int64_t*>(h->ws + h->L.cell0q)),
                     "propagation table");
     if (!rc) {
-        h->q_dirty = false;
+        h->q_dirty = h->q_params = false;
         h->q_end = (int)std::min<int64_t>(t_end, INT_MAX);
     }
     return rc;
@@ -978,7 +987,7 @@ int sim_set_params(sim_handle* h, const sim_params* p) {
         if (rc) return rc;
     }
     h->adj_T = -1;  // adjoint jobs copy the parameters
-    h->q_dirty = true;
+    h->q_dirty = h->q_params = true;
     if (h->calib() && h->step != 0) h->stale = true;
     return SIM_OK;
 }
@@ -1025,7 +1034,7 @@ int sim_set_state(sim_handle* h, int32_t s, const uint8_t* in, int32_t step) {
     if (!rc) rc = h->hip(fs::launch_set_state(h->st, J, in, J.planes[h->parity], h->d_err()),
                          "set state");
     if (!rc) rc = refresh_worklist(h, true);
-    if (!rc) rc = take_origin(h, step);
+    if (!rc) rc = take_origin(h, step, false);
     int bad = 0;
     if (!rc) rc = h->hip(hipMemcpyAsync(&bad, h->d_err(), sizeof(int), hipMemcpyDeviceToHost,
                                         h->st), "read error flag");
@@ -1229,7 +1238,7 @@ int sim_set_wind(sim_handle* h, int32_t s, const float* wind_speed, const float*
                                         h->st), "read error flag");
     if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
     if (rc) return rc;
-    h->q_dirty = true;
+    h->q_dirty = h->q_params = true;
     h->d[s].f.wind_speed = wind_speed;
     h->d[s].f.wind_dir_deg = wind_dir_deg;
     h->d[s].f.wind_speed_scalar = wind_speed_scalar;
@@ -1248,7 +1257,7 @@ int sim_ignite(sim_handle* h, int32_t s, const int32_t* cells, int32_t count) {
     if (count == 0) return SIM_OK;
     int rc = h->hip(fs::launch_ignite(h->st, h->job[s], cells, count), "ignite");
     if (!rc) rc = refresh_worklist(h, false);   // both buffers were written
-    if (!rc) rc = take_origin(h, h->step);
+    if (!rc) rc = take_origin(h, h->step, false);
     return rc;
 }
 

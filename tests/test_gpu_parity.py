@@ -1118,6 +1118,54 @@ def test_table_region_follows_the_state(Sim):
     check_light_cone(gstate(sim), st2, ties2, 25)
 
 
+def test_table_kept_across_resets(Sim):
+    """A reset keeps the propagation table when it was built around the reset
+    state under the current parameters and wind; anything else rebuilds it.
+    Every run below equals a fresh handle of the same scenario bit for bit and
+    the oracle outside near-tie light cones: new seeds on the kept table, a
+    longer run than the table covers, new parameters, new wind, and a reset
+    after a state set far from the ignition."""
+    base = synth.make_lakes(150, 170, 81, T=60, n_ignitions=1)
+    sim = Sim([base])
+    sim.run(30)
+
+    def check(sc, T, what):
+        sim.run(T)
+        g = sim.get_state(0).cpu().numpy()
+        fresh = Sim([sc])
+        fresh.run(T)
+        assert np.array_equal(g, fresh.get_state(0).cpu().numpy()), what
+        states, ties = oracle_traj(sc, T)
+        say(what, "differing cells:", check_light_cone(synth.decode_planes(g), states, ties, T))
+
+    sc = dataclasses.replace(base, seed=7)
+    sim.reset([7])                       # table kept: same origin, parameters, wind
+    check(sc, 30, "kept table, new seed")
+    sc = dataclasses.replace(base, seed=8)
+    sim.reset([8])
+    check(sc, 60, "run past the kept table's steps")
+    sc = dataclasses.replace(base, seed=9, p_h=0.45, c1=0.3)
+    sim.set_params([(sc.p_h, sc.a, sc.c1, sc.c2, sc.p_continue)])
+    sim.reset([9])
+    check(sc, 40, "new parameters")
+    w = synth.make_lakes(150, 170, 82, T=60)
+    sc = dataclasses.replace(sc, seed=10)
+    sc.wind_speed, sc.wind_dir = w.wind_speed, w.wind_dir
+    sim.set_wind(0, w.wind_speed, w.wind_dir)
+    sim.reset([10])
+    check(sc, 40, "new wind")
+    sim.reset([10])
+    check(sc, 40, "kept table after the wind change")
+    S = np.zeros((base.H, base.W), np.uint8)
+    S[140:145, 160:165] = 1
+    S[base.p_veg <= -1] = 0
+    sim.set_state(0, synth.encode_planes(S), 0)
+    sim.run(5)
+    sc = dataclasses.replace(sc, seed=11)
+    sim.reset([11])                      # the table was built around S: rebuilt
+    check(sc, 50, "reset after a state set elsewhere")
+
+
 def test_table_blocks_around_distant_fires(Sim):
     """Fires in opposite corners of a grid many 32 x 32 blocks wide: the table
     covers the blocks within reach of each fire, not the box between them.
