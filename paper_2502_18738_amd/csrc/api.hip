@@ -986,7 +986,8 @@ int sim_set_params(sim_handle* h, const sim_params* p) {
         int rc = h->hip(fs::launch_set_params(h->st, h->d_jobs(), pb), "set params");
         if (rc) return rc;
     }
-    h->adj_T = -1;  // adjoint jobs copy the parameters
+    // (the adjoint's segment jobs take the new parameters on the device before
+    // their next recompute)
     h->q_dirty = h->q_params = true;
     if (h->calib() && h->step != 0) h->stale = true;
     return SIM_OK;
@@ -1009,7 +1010,6 @@ int sim_reset(sim_handle* h, const uint64_t* seeds) {
             int rc = h->hip(fs::launch_set_seeds(h->st, h->d_jobs(), sb), "set seeds");
             if (rc) return rc;
         }
-        h->adj_T = -1;
     }
     h->stale = false;
     return reset_state(h);
@@ -1132,13 +1132,18 @@ int adjoint(sim_handle* h, const float* lam, double* grad) {
         return r;
     };
     if (h->adj_method == 1) return gradient_pass(true);
+    // the segment jobs depend on T and the tiling only; parameters and seeds
+    // come from the scenario jobs on the device, so a new gradient step of the
+    // same length needs no host rebuild, upload or synchronisation
     int rc = SIM_OK;
     if (h->adj_T != T) rc = build_adjoint(h, T);
     if (rc) return rc;
     auto* d_adj = reinterpret_cast<fs::DevScen*>(h->ws + h->L.adj_jobs);
     auto* d_adj_tiles = reinterpret_cast<int32_t*>(h->ws + h->L.adj_tile_job);
     const int njobs = (int)h->adj.size();
-    rc = h->hip(fs::launch_ckpt_load(h->st, d_adj, njobs, h->max_words), "load checkpoints");
+    rc = h->hip(fs::launch_adj_params(h->st, d_adj, njobs, njobs / h->n, h->d_jobs()),
+                "adjoint parameters");
+    if (!rc) rc = h->hip(fs::launch_ckpt_load(h->st, d_adj, njobs, h->max_words), "load checkpoints");
     if (!rc) rc = h->hip(fs::launch_flags_init(h->st, d_adj, d_adj_tiles, h->adj_ntiles, 0,
                                                h->sh), "adjoint flags");
     auto* amask = reinterpret_cast<unsigned long long*>(h->ws + h->L.adj_masks);

@@ -198,6 +198,10 @@ struct SeedBlock {
     uint32_t lo[64], hi[64];
 };
 hipError_t launch_set_seeds(hipStream_t st, DevScen* d_jobs, const SeedBlock& sb);
+// The checkpoint adjoint's per-segment jobs (nseg per scenario, scenario-major)
+// take the current parameters and Philox keys of their scenario's job.
+hipError_t launch_adj_params(hipStream_t st, DevScen* d_adj, int32_t nadj, int32_t nseg,
+                             const DevScen* d_jobs);
 hipError_t launch_pignite(hipStream_t st, const DevScen* d_job, const DevScen& job,
                           int32_t parity, float* out);
 // Eq. 10 for each of the n scenarios (accumulators from their descriptors;

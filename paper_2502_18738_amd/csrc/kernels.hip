@@ -2047,6 +2047,25 @@ __global__ void k_set_seeds(DevScen* jobs, SeedBlock sb) {
     }
 }
 
+// Segment k of the checkpoint adjoint belongs to scenario k / nseg: it takes
+// that scenario's parameters and Philox keys (everything else in its
+// descriptor is fixed by the run's length and the tiling).
+__global__ void k_adj_params(DevScen* adj, int32_t nadj, int32_t nseg,
+                             const DevScen* __restrict__ jobs) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nadj) {
+        const DevScen& F = jobs[k / nseg];
+        DevScen& J = adj[k];
+        J.p_h = F.p_h;
+        J.a = F.a;
+        J.c1 = F.c1;
+        J.c2 = F.c2;
+        J.p_continue = F.p_continue;
+        J.seed_lo = F.seed_lo;
+        J.seed_hi = F.seed_hi;
+    }
+}
+
 // --------------------------------------------------------------- launchers
 
 hipError_t launch_ckpt_save(hipStream_t st, const DevScen* d_jobs, int32_t n, int32_t parity,
@@ -2071,6 +2090,14 @@ hipError_t launch_set_params(hipStream_t st, DevScen* d_jobs, const ParamBlock& 
 
 hipError_t launch_set_seeds(hipStream_t st, DevScen* d_jobs, const SeedBlock& sb) {
     hipLaunchKernelGGL(k_set_seeds, dim3(1), dim3(64), 0, st, d_jobs, sb);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_params(hipStream_t st, DevScen* d_adj, int32_t nadj, int32_t nseg,
+                             const DevScen* d_jobs) {
+    if (nadj <= 0 || nseg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_params, dim3((nadj + 255) / 256), dim3(256), 0, st, d_adj, nadj,
+                       nseg, d_jobs);
     return hipGetLastError();
 }
 

@@ -1048,6 +1048,45 @@ def test_adjoint_refused_after_midrun_parameter_change(Sim):
     assert float(L2[0]) == float(L0[0]) and np.array_equal(g2.cpu().numpy(), g0.cpu().numpy())
 
 
+@pytest.mark.parametrize("shape", ["32x8d10s3t256", "32x4d8s1t256", "32x2d32s1t512"])
+def test_gradient_steps_with_new_parameters_and_seeds(Sim, shape):
+    """Gradient steps as a calibration loop takes them (new parameters and
+    new seeds before each reset, the same run length): the checkpoint
+    adjoint keeps its per-segment jobs and takes the parameters and seeds on
+    the device. Every step equals a fresh handle at that step's parameters
+    and seeds bit for bit, and the last the oracle's loss and gradient."""
+    T = 30
+    scs, ys = zip(*[calib_case(70, 90, 21 + b, T) for b in range(2)])
+    y = np.concatenate([t.ravel() for t in ys])
+    ex = GRAD_SHAPES[shape]
+    sim = Sim(list(scs), calib=True, T_max=T, ckpt_every=10, exec=ex)
+    steps = [((0.55, 0.04, 0.05, 0.12), 3), ((0.62, 0.05, 0.07, 0.09), 4),
+             ((0.48, 0.06, 0.04, 0.11), 5)]
+    for th, sd in steps:
+        par = [th + (sc.p_continue,) for sc in scs]
+        seeds = [sd * 100 + b for b in range(len(scs))]
+        sim.set_params(par)
+        sim.reset(seeds)
+        sim.run(T)
+        L, g = sim.loss_grad(y, 0)
+        fresh_s = [dataclasses.replace(sc.with_params(*th), seed=seeds[b])
+                   for b, sc in enumerate(scs)]
+        fresh = Sim(fresh_s, calib=True, T_max=T, ckpt_every=10, exec=ex)
+        fresh.run(T)
+        Lf, gf = fresh.loss_grad(y, 0)
+        assert np.array_equal(L.cpu().numpy(), Lf.cpu().numpy()), (th, sd)
+        assert np.array_equal(g.cpu().numpy(), gf.cpu().numpy()), (th, sd)
+    for b, s in enumerate(fresh_s):
+        r = oracle.run(s, T, want_yhat=True, tie_eps=TIE)
+        assert_same_trajectory(gstate(sim, b), r["S"], f"scenario {b} ({r['ties']} near ties)")
+        Lo, lam = oracle.loss(r["yhat"], ys[b], 0)
+        assert float(L[b]) == pytest.approx(Lo, rel=1e-6)
+        go = oracle.grad(s, T, lam)
+        gb = g[b].cpu().numpy()
+        scale = np.abs(go).max()
+        assert np.all(np.abs(gb - go) <= 1e-4 * np.abs(go) + 1e-6 * scale), (gb, go)
+
+
 def test_non_default_stream(Sim):
     """A handle on its own stream, called from code running on another
     stream, gives the same results as one on the current stream."""
