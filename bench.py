@@ -472,14 +472,23 @@ def leg_cpu(args, s2, synth):
     one(s2, 40, "4096x4096, steps 1-40 (sample)", 1)
     one(s0, s0.T, "128x128, 100 steps (full run)", threads)
     one(s1, s1.T, "1024x1024, 500 steps (full run)", threads)
-    main = one(s2, 200, "4096x4096, steps 1-200 (sample)", threads)
+    main = one(s2, s2.T, "4096x4096, 1000 steps (full run)", threads)
     oracle.set_threads(1)
+    # the larger workloads at the all-core rate of the full 4096 x 4096 run
+    # (the oracle's cost per cell-step does not depend on the fire)
+    rate = main["G_cell_steps_per_s"] * 1e9
+    c3 = sum(h * w for h, w in synth.config3_sizes())
+    est = [{"workload": "256 scenarios, sides 256-2048, 300 steps (forward)",
+            "cell_steps": c3 * 300, "seconds": round(c3 * 300 / rate, 1)},
+           {"workload": "64 scenarios 1024x1024, 200 steps (forward of one gradient step)",
+            "cell_steps": 64 * 1024 * 1024 * 200,
+            "seconds": round(64 * 1024 * 1024 * 200 / rate, 1)}]
     return {"value": main["G_cell_steps_per_s"], "unit": "G cell-steps/s",
             "cores": main["threads"], "kind": "oracle",
-            "sample": "4096x4096 main workload, steps 1-200 from the ignition patch, FP64 C "
-                      f"loop with rows split over {main['threads']} threads",
+            "sample": "the whole 4096x4096 main workload (1000 steps from the ignition patch), "
+                      f"FP64 C loop with rows split over {main['threads']} threads",
             "host": {"cpu_model": model, "cpus_available": avail},
-            "runs": rows}
+            "runs": rows, "extrapolated": est}
 
 
 def main():
