@@ -1213,7 +1213,7 @@ int sim_loss_grad(sim_handle* h, const uint8_t* target, int32_t kind, double* lo
     float* lam = reinterpret_cast<float*>(h->ws + h->L.lam);
     int rc = h->hip(fs::launch_loss(h->st, h->d_jobs(),
                                     reinterpret_cast<const int64_t*>(h->ws + h->L.cell0), h->n,
-                                    h->L.max_h, target, kind, lam,
+                                    h->L.max_h, h->parity, target, kind, lam,
                                     reinterpret_cast<int*>(h->ws + h->L.box),
                                     reinterpret_cast<double*>(h->ws + h->L.part), loss),
                     "loss");

@@ -206,11 +206,13 @@ hipError_t launch_pignite(hipStream_t st, const DevScen* d_job, const DevScen& j
                           int32_t parity, float* out);
 // Eq. 10 for each of the n scenarios (accumulators from their descriptors;
 // y and lambda concatenated, scenario i at d_cell0[i]): writes lambda =
-// dL/dyhat and loss_out[i].  d_box holds 4 n ints, d_part
-// 2 n ceil(max_h / 4) doubles.
+// dL/dyhat and loss_out[i].  The crop box comes from the state in
+// planes[parity] (calibration handles: the accumulator is non-zero exactly on
+// the cells that burn or burned) and the target.  d_box holds 4 n ints,
+// d_part 2 n ceil(max_h / 4) doubles.
 hipError_t launch_loss(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
-                       int32_t max_h, const uint8_t* y, int32_t kind, float* lambda, int* d_box,
-                       double* d_part, double* loss_out);
+                       int32_t max_h, int32_t parity, const uint8_t* y, int32_t kind,
+                       float* lambda, int* d_box, double* d_part, double* loss_out);
 // grad[s] = sum of gpart[g] over blocks g in [ranges[s], ranges[s+1]).
 hipError_t launch_grad_reduce(hipStream_t st, const double* gpart, const int32_t* d_ranges,
                               int32_t n, double* grad);

@@ -1726,18 +1726,23 @@ k_grad_reduce(const double* __restrict__ gpart, const int32_t* __restrict__ rang
 // the concatenated arrays; box holds 4 ints and part 2 * maxparts doubles per
 // scenario.
 
-// Bounding box of (yhat != 0) | (y != 0): box = {rmin, rmax, cmin, cmax}.  A
-// block strides over its scenario, reduces its own box in LDS and merges it
-// with four atomics, so the atomics do not contend per cell.  Rows of a
-// multiple of 4 cells with a 4-byte aligned target are read 4 cells at a time
-// (16-byte yhat, 4-byte target loads), other grids cell by cell.
+// Bounding box of (yhat != 0) | (y != 0): box = {rmin, rmax, cmin, cmax}.  In
+// a calibration handle the accumulator is non-zero exactly on the cells that
+// burn or burned (1 on the initial burning cells, p_ignite > 0 at an
+// ignition, and no outside states or ignitions), so the box reads the 2-bit
+// state planes instead of the FP32 accumulator.  A block strides over its
+// scenario, reduces its own box in LDS and merges it with four atomics, so
+// the atomics do not contend per cell.  Rows of a multiple of 4 cells with a
+// 4-byte aligned target are read 4 cells at a time (one 4-byte target load
+// and the plane words holding the quad), other grids cell by cell.
 __global__ void __launch_bounds__(256)
 k_loss_box(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0,
-           const uint8_t* __restrict__ y_all, int* __restrict__ box_all) {
+           const uint8_t* __restrict__ y_all, int32_t parity, int* __restrict__ box_all) {
     const DevScen& J = jobs[blockIdx.y];
-    const float* yhat = J.yhat;
     const uint8_t* y = y_all + cell0[blockIdx.y];
-    const int W = J.W;
+    const int W = J.W, pitch = J.pitch;
+    const FS_GLOBAL uint32_t* burning = gmem(J.planes[parity]);
+    const FS_GLOBAL uint32_t* burned = burning + (int64_t)J.H * pitch;
     int v[4] = {INT_MAX, -1, INT_MAX, -1};
     auto hit = [&](int r, int c) {
         v[0] = min(v[0], r);
@@ -1747,21 +1752,20 @@ k_loss_box(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0,
     };
     if ((W & 3) == 0 && ((uintptr_t)y & 3u) == 0) {
         const int64_t nq = (int64_t)J.H * W / 4;
-        const FS_GLOBAL fs_f4* y4 = gmem(reinterpret_cast<const fs_f4*>(yhat));
         const FS_GLOBAL uint32_t* t4 = gmem(reinterpret_cast<const uint32_t*>(y));
         const int64_t q_first = (int64_t)blockIdx.x * 256 + threadIdx.x;
         const int64_t step = 4 * (int64_t)gridDim.x * 256;
         const int dR = (int)(step / W), dC = (int)(step - (int64_t)dR * W);
         int r = (int)((4 * q_first) / W), c = (int)(4 * q_first - (int64_t)r * W);
         for (int64_t q = q_first; q < nq; q += step / 4) {
-            const fs_f4 a = y4[q];
+            // the quad's 4 cells lie in one plane word (c is a multiple of 4)
+            const int64_t o = (int64_t)r * pitch + (c >> 5);
             const uint32_t b = t4[q];
+            const uint32_t st = ((burning[o] | burned[o]) >> (c & 31)) & 0xFu;
             // the quad's cells that count, one bit each: one update of the row
             // bounds, the columns from the first and last such cell
-            const uint32_t nz = ((a.x != 0.f || (b & 0xFFu)) ? 1u : 0u) |
-                                ((a.y != 0.f || (b & 0xFF00u)) ? 2u : 0u) |
-                                ((a.z != 0.f || (b & 0xFF0000u)) ? 4u : 0u) |
-                                ((a.w != 0.f || (b & 0xFF000000u)) ? 8u : 0u);
+            const uint32_t nz = st | ((b & 0xFFu) ? 1u : 0u) | ((b & 0xFF00u) ? 2u : 0u) |
+                                ((b & 0xFF0000u) ? 4u : 0u) | ((b & 0xFF000000u) ? 8u : 0u);
             if (nz) {
                 v[0] = min(v[0], r);
                 v[1] = max(v[1], r);
@@ -1778,8 +1782,9 @@ k_loss_box(const DevScen* __restrict__ jobs, const int64_t* __restrict__ cell0,
     } else {
         for (int r = blockIdx.x; r < J.H; r += gridDim.x)
             for (int c = threadIdx.x; c < W; c += 256) {
-                const int64_t j = (int64_t)r * W + c;
-                if (yhat[j] != 0.f || y[j] != 0) hit(r, c);
+                const int64_t o = (int64_t)r * pitch + (c >> 5);
+                const bool st = (((burning[o] | burned[o]) >> (c & 31)) & 1u) != 0;
+                if (st || y[(int64_t)r * W + c] != 0) hit(r, c);
             }
     }
     __shared__ int sh[4][256];
@@ -2288,12 +2293,13 @@ hipError_t launch_grad_reduce(hipStream_t st, const double* gpart, const int32_t
 }
 
 hipError_t launch_loss(hipStream_t st, const DevScen* d_jobs, const int64_t* d_cell0, int32_t n,
-                       int32_t max_h, const uint8_t* y, int32_t kind, float* lambda, int* d_box,
-                       double* d_part, double* loss_out) {
+                       int32_t max_h, int32_t parity, const uint8_t* y, int32_t kind,
+                       float* lambda, int* d_box, double* d_part, double* loss_out) {
     if (n <= 0) return hipSuccess;
     const int maxparts = (max_h + 3) / 4;
     hipLaunchKernelGGL(k_box_init, dim3(1), dim3(256), 0, st, d_jobs, n, d_box);
-    hipLaunchKernelGGL(k_loss_box, dim3(128, n), dim3(256), 0, st, d_jobs, d_cell0, y, d_box);
+    hipLaunchKernelGGL(k_loss_box, dim3(128, n), dim3(256), 0, st, d_jobs, d_cell0, y, parity,
+                       d_box);
     hipLaunchKernelGGL(k_loss_terms, dim3(maxparts, n), dim3(256), 0, st, d_jobs, d_cell0, y,
                        kind, d_box, lambda, d_part, maxparts);
     hipLaunchKernelGGL(k_loss_final, dim3(n), dim3(256), 0, st, d_jobs, kind, d_box, d_part,
