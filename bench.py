@@ -318,6 +318,43 @@ def leg_calib(args, torch, Sim, synth):
     tune.run(100)
     cex = tune.autotune(ck)   # one checkpoint segment: the launch pattern of a calibration run
     del tune
+    # The forward probe does not see the checkpoint adjoint's recompute, which
+    # launches the tiles of every segment together and pays a dispatch cost
+    # per launch: settle the depth on whole gradient steps, for the probe's
+    # tile at each halo depth (a segment's steps spread evenly over the fewest
+    # launches the halo allows: 7, 10 or 20 steps for halos of 8, 16, 32)
+    from paper_2502_18738_amd import SimError
+    p0 = [list(start[b]) + [true_s[b].p_continue] for b in range(n)]
+    depths = {cex["depth"]}
+    for km in (8, 16, 32):
+        depths.add(min(-(-ck // -(-ck // km)), cex["tile_rows"]))
+    best = None
+    for d in sorted(depths):
+        ex = dict(cex, depth=d)
+        try:
+            probe = Sim(true_s, calib=True, T_max=T, ckpt_every=ck, exec=ex)
+        except SimError:
+            continue            # no halo of that depth compiled for this tile
+
+        def probe_step(i):
+            probe.set_params(p0)
+            probe.reset([500 + i] * n)
+            probe.run(T)
+            probe.loss_grad(target, 0)
+
+        probe_step(0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(3):
+            probe_step(i + 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log("calibration depth", d, round(dt / 3 * 1e3, 3), "ms per gradient step")
+        del probe
+        if best is None or dt < best[0]:
+            best = (dt, ex)
+    if best:
+        cex = best[1]
     sim = Sim(true_s, calib=True, T_max=T, ckpt_every=ck, exec=cex)
     theta = torch.tensor(start, dtype=torch.float32, device="cuda", requires_grad=True)
     opt = torch.optim.AdamW([theta], lr=5e-3)
@@ -353,7 +390,9 @@ def leg_calib(args, torch, Sim, synth):
                             "ms_per_grad_step": round(wall_tm / K * 1e3, 2)},
         "config": {"workload": "64 scenarios 1024x1024, 200 steps, checkpoints every 20, "
                                "BCE loss, AdamW lr 5e-3 with clamps",
-                   "exec": cex},
+                   "exec": cex,
+                   "exec_from": "tile from a forward autotune over one checkpoint segment, "
+                                "depth from whole gradient steps at each halo depth"},
     }
 
 
