@@ -358,14 +358,13 @@ def leg_calib(args, torch, Sim, synth):
     sim = Sim(true_s, calib=True, T_max=T, ckpt_every=ck, exec=cex)
     theta = torch.tensor(start, dtype=torch.float32, device="cuda", requires_grad=True)
     opt = torch.optim.AdamW([theta], lr=5e-3)
-    pc = torch.tensor([s.p_continue for s in true_s], dtype=torch.float32)
     lo = torch.tensor([0.2, 0.0, 0.0, 0.0], device="cuda")
     hi = torch.tensor([1.0, 1.0, 1.0, 1.0], device="cuda")
     step = [0]
 
     def grad_step():
-        p = theta.detach().cpu()
-        sim.set_params(torch.cat([p, pc[:, None]], 1).tolist())
+        # theta goes to the library from device memory (no host round trip)
+        sim.set_params_device(theta.detach())
         sim.reset([1000 + step[0]] * n)
         sim.run(T)
         loss, g = sim.loss_grad(target, 0)
@@ -380,6 +379,8 @@ def leg_calib(args, torch, Sim, synth):
     wall, gpu = timed(grad_step, K, 1, torch)
     sim.set_adjoint("timemap")
     wall_tm, _ = timed(grad_step, K, 1, torch)
+    if sim.params_rejected():
+        raise RuntimeError("the library rejected parameter rows during the calibration leg")
     cells = 1024 * 1024 * n
     return {
         "metric": "calibration grad-steps/s", "value": round(K / wall, 3),

@@ -233,6 +233,23 @@ SIM_API int sim_get_step(const sim_handle* h, int32_t* step);
  * SIM_E_STATE until the next sim_reset. */
 SIM_API int sim_set_params(sim_handle* h, const sim_params* per_scenario);
 
+/* The calibrated parameters theta = (p_h, a, c1, c2) of Algorithm 1 from
+ * device memory, for a calibration loop whose optimiser step runs on the GPU
+ * (no host round trip between gradient steps).  `theta`: device pointer,
+ * 4-byte aligned, n rows of 4 float32, read on the handle's stream in stream
+ * order (the caller orders its writes before the call, e.g. on the same
+ * stream).  p_continue is kept.  Rows are checked on the device: a row with a
+ * non-finite value or p_h < 0 leaves that scenario's parameters unchanged
+ * and is counted; sim_params_rejected returns the count.  Otherwise as
+ * sim_set_params (the propagation table is rebuilt, and in calibration mode a
+ * change after step 0 makes the adjoint wait for the next sim_reset). */
+SIM_API int sim_set_params_device(sim_handle* h, const float* theta);
+
+/* Number of parameter rows sim_set_params_device rejected since the handle
+ * was made or the last call of this function (which clears it); waits for
+ * the handle's stream. */
+SIM_API int sim_params_rejected(sim_handle* h, int32_t* count);
+
 /* Restore every scenario to init_burning at step 0 and clear the
  * accumulator (Algorithm 1, model.reset).  `seeds` (host, n entries) replaces
  * the Philox keys, or is NULL to keep them.  A propagation table built around

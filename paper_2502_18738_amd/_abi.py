@@ -76,7 +76,8 @@ EXPORTS = (
     "sim_pignite", "sim_accumulator", "sim_adjoint", "sim_loss_grad", "sim_stats",
     "sim_last_error", "sim_destroy", "sim_version", "sim_autotune", "sim_use_graphs",
     "sim_set_adjoint", "sim_set_wind", "sim_ignite", "sim_counts", "sim_overlap", "sim_arrival", "sim_tielog",
-    "sim_metrics", "sim_prepare", "sim_init_static",
+    "sim_metrics", "sim_prepare", "sim_init_static", "sim_set_params_device",
+    "sim_params_rejected",
 )
 
 _lib = None
@@ -109,6 +110,8 @@ def load():
         "sim_step": (ctypes.c_int, [H]),
         "sim_get_step": (ctypes.c_int, [H, ctypes.POINTER(i32)]),
         "sim_set_params": (ctypes.c_int, [H, ctypes.POINTER(sim_params)]),
+        "sim_set_params_device": (ctypes.c_int, [H, vp]),
+        "sim_params_rejected": (ctypes.c_int, [H, ctypes.POINTER(i32)]),
         "sim_reset": (ctypes.c_int, [H, ctypes.POINTER(ctypes.c_uint64)]),
         "sim_get_state": (ctypes.c_int, [H, i32, vp]),
         "sim_set_state": (ctypes.c_int, [H, i32, vp, i32]),

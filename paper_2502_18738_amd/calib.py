@@ -18,7 +18,7 @@ from typing import Optional, Sequence
 
 import torch
 
-from ._abi import SIM_LOSS_BCE
+from ._abi import SIM_E_PARAM, SIM_LOSS_BCE, SimError
 from .sim import Sim
 
 # Clamp ranges of Algorithm 1: p_h in [0.2, 1], a, c1, c2 in [0, 1].
@@ -68,7 +68,10 @@ def calibrate(sim: Sim, target, theta0, *, T: int, steps: int = 50, lr: float = 
 
     Returns (theta, history) where history holds (loss per scenario, theta)
     after every step.  Gradient step g uses Philox seed ``seed0 + g`` for all
-    scenarios (a new epoch seed each step).
+    scenarios (a new epoch seed each step).  The parameters go to the library
+    from device memory and the history stays on the device until the end, so
+    the loop never waits for the host; a parameter row the library rejected
+    (non-finite or p_h < 0) raises ``SimError`` after the loop.
     """
     theta = torch.as_tensor(theta0, dtype=torch.float32, device=sim.device).clone()
     theta.requires_grad_(True)
@@ -76,9 +79,7 @@ def calibrate(sim: Sim, target, theta0, *, T: int, steps: int = 50, lr: float = 
     history = []
     y = torch.as_tensor(target, device=sim.device).to(torch.uint8).view(-1)
     for g in range(steps):
-        p = theta.detach().to("cpu")
-        rows = [tuple(r) + (pc,) for r, pc in zip(p.tolist(), sim.p_continue)]
-        sim.set_params(rows)
+        sim.set_params_device(theta.detach())
         sim.reset([seed0 + g] * sim.n)
         sim.run(int(T))
         loss, grad = sim.loss_grad(y, loss_kind)
@@ -86,10 +87,14 @@ def calibrate(sim: Sim, target, theta0, *, T: int, steps: int = 50, lr: float = 
         opt.step()
         opt.zero_grad(set_to_none=True)
         clamp_(theta)
-        history.append((loss.detach().cpu(), theta.detach().cpu().clone()))
+        history.append((loss.detach().clone(), theta.detach().clone()))
         if callback is not None:
             callback(g, loss, theta)
-    return theta.detach(), history
+    bad = sim.params_rejected()
+    if bad:
+        raise SimError(SIM_E_PARAM, f"{bad} parameter rows were rejected during calibration "
+                                    "(non-finite or p_h < 0)")
+    return theta.detach(), [(l.cpu(), t.cpu()) for l, t in history]
 
 
 def calibrate_sequence(sim: Sim, observations, theta0, *, interval: int, epochs: int = 1,

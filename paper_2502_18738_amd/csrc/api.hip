@@ -256,6 +256,9 @@ struct sim_handle {
     // built; q_reset: the table's origin is the reset state (the same burning
     // cells after every reset), so a reset may keep a table built from it
     bool q_params = true, q_reset = false;
+    // the parameters were last set on the device (sim_set_params_device): the
+    // host copies in job[] and d[] are stale until pull_theta
+    bool theta_dev = false;
     // calibration mode: the parameters changed after the run started, so the
     // checkpoints / time maps no longer match the parameters an adjoint would
     // differentiate; cleared by sim_reset
@@ -311,8 +314,33 @@ fs::TileShape shape_of(const sim_exec& e) {
 
 int refresh_worklist(sim_handle* h, bool dup);
 
+// Bring parameters set on the device back into the host copies of the jobs
+// (before the host copies are uploaded again).
+int pull_theta(sim_handle* h) {
+    if (!h->theta_dev) return SIM_OK;
+    std::vector<fs::DevScen> dev((size_t)h->n);
+    int rc = h->hip(hipMemcpyAsync(dev.data(), h->d_jobs(), sizeof(fs::DevScen) * h->n,
+                                   hipMemcpyDeviceToHost, h->st), "read parameters");
+    if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (rc) return rc;
+    for (int i = 0; i < h->n; ++i) {
+        fs::DevScen& J = h->job[i];
+        J.p_h = dev[i].p_h;
+        J.a = dev[i].a;
+        J.c1 = dev[i].c1;
+        J.c2 = dev[i].c2;
+        h->d[i].params.p_h = J.p_h;
+        h->d[i].params.a = J.a;
+        h->d[i].params.c1 = J.c1;
+        h->d[i].params.c2 = J.c2;
+    }
+    h->theta_dev = false;
+    return SIM_OK;
+}
+
 // Recompute tile grids and the tile -> job table of the forward jobs.
 int rebuild_tiles(sim_handle* h) {
+    if (int rc = pull_theta(h)) return rc;
     int32_t g = 0;
     h->tile_job.clear();
     for (int i = 0; i < h->n; ++i) {
@@ -528,7 +556,8 @@ int init_handle(sim_handle** out, const sim_desc* descs, int32_t n, void* worksp
         h->max_words = std::max<int64_t>(h->max_words, s.PW);
     }
 
-    rc = h->hip(hipMemsetAsync(h->d_err(), 0, sizeof(int), h->st), "clear error flag");
+    // error flag and count of rejected device parameter rows
+    rc = h->hip(hipMemsetAsync(h->d_err(), 0, 2 * sizeof(int), h->st), "clear error flag");
     for (int i = 0; i < n && !rc; ++i) {
         const sim_desc& d = descs[i];
         fs::DevScen& J = h->job[i];
@@ -988,9 +1017,36 @@ int sim_set_params(sim_handle* h, const sim_params* p) {
     }
     // (the adjoint's segment jobs take the new parameters on the device before
     // their next recompute)
+    h->theta_dev = false;
     h->q_dirty = h->q_params = true;
     if (h->calib() && h->step != 0) h->stale = true;
     return SIM_OK;
+}
+
+int sim_set_params_device(sim_handle* h, const float* theta) {
+    if (!h) return SIM_E_ARG;
+    if (!theta) return h->fail(SIM_E_ARG, "theta is NULL");
+    if ((uintptr_t)theta & 3u) return h->fail(SIM_E_ARG, "theta must be 4-byte aligned");
+    int rc = h->hip(fs::launch_set_theta(h->st, h->d_jobs(), h->n, theta, h->d_err() + 1),
+                    "set parameters on the device");
+    if (rc) return rc;
+    h->theta_dev = true;
+    h->q_dirty = h->q_params = true;
+    if (h->calib() && h->step != 0) h->stale = true;
+    return SIM_OK;
+}
+
+int sim_params_rejected(sim_handle* h, int32_t* count) {
+    if (!h) return SIM_E_ARG;
+    if (!count) return h->fail(SIM_E_ARG, "count is NULL");
+    int v = 0;
+    int rc = h->hip(hipMemcpyAsync(&v, h->d_err() + 1, sizeof(int), hipMemcpyDeviceToHost,
+                                   h->st), "read rejected count");
+    if (!rc) rc = h->hip(hipStreamSynchronize(h->st), "synchronise");
+    if (!rc) rc = h->hip(hipMemsetAsync(h->d_err() + 1, 0, sizeof(int), h->st),
+                         "clear rejected count");
+    if (!rc) *count = v;
+    return rc;
 }
 
 int sim_reset(sim_handle* h, const uint64_t* seeds) {

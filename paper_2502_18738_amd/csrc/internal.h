@@ -198,6 +198,10 @@ struct SeedBlock {
     uint32_t lo[64], hi[64];
 };
 hipError_t launch_set_seeds(hipStream_t st, DevScen* d_jobs, const SeedBlock& sb);
+// theta: device, n rows of (p_h, a, c1, c2) for the n jobs; rows that are not
+// finite or have p_h < 0 keep the job's parameters and add 1 to *rejected.
+hipError_t launch_set_theta(hipStream_t st, DevScen* d_jobs, int32_t n, const float* theta,
+                            int* rejected);
 // The checkpoint adjoint's per-segment jobs (nseg per scenario, scenario-major)
 // take the current parameters and Philox keys of their scenario's job.
 hipError_t launch_adj_params(hipStream_t st, DevScen* d_adj, int32_t nadj, int32_t nseg,

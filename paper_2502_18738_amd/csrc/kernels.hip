@@ -2052,6 +2052,26 @@ __global__ void k_set_seeds(DevScen* jobs, SeedBlock sb) {
     }
 }
 
+// theta (device, n rows of p_h, a, c1, c2): a row whose values are finite with
+// p_h >= 0 replaces the scenario's parameters (p_continue is kept); any other
+// row leaves them unchanged and is counted in *rejected.
+__global__ void k_set_theta(DevScen* jobs, int32_t n, const float* __restrict__ theta,
+                            int* __restrict__ rejected) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float p_h = theta[4 * i], a = theta[4 * i + 1], c1 = theta[4 * i + 2],
+                c2 = theta[4 * i + 3];
+    if (isfinite(p_h) && isfinite(a) && isfinite(c1) && isfinite(c2) && p_h >= 0.f) {
+        DevScen& J = jobs[i];
+        J.p_h = p_h;
+        J.a = a;
+        J.c1 = c1;
+        J.c2 = c2;
+    } else {
+        atomicAdd(rejected, 1);
+    }
+}
+
 // Segment k of the checkpoint adjoint belongs to scenario k / nseg: it takes
 // that scenario's parameters and Philox keys (everything else in its
 // descriptor is fixed by the run's length and the tiling).
@@ -2095,6 +2115,14 @@ hipError_t launch_set_params(hipStream_t st, DevScen* d_jobs, const ParamBlock& 
 
 hipError_t launch_set_seeds(hipStream_t st, DevScen* d_jobs, const SeedBlock& sb) {
     hipLaunchKernelGGL(k_set_seeds, dim3(1), dim3(64), 0, st, d_jobs, sb);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_theta(hipStream_t st, DevScen* d_jobs, int32_t n, const float* theta,
+                            int* rejected) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_theta, dim3((n + 255) / 256), dim3(256), 0, st, d_jobs, n, theta,
+                       rejected);
     return hipGetLastError();
 }
 

@@ -215,6 +215,26 @@ class Sim:
             self._check(self._lib.sim_set_params(self._h, arr))
         self.p_continue = [float(np.float32(r[4])) for r in rows]
 
+    def set_params_device(self, theta: torch.Tensor):
+        """theta: (n, 4) tensor of (p_h, a, c1, c2) on the handle's device,
+        read by the library in stream order (no host round trip); p_continue
+        is kept.  Rows the library rejects (non-finite, p_h < 0) keep their
+        parameters and are counted by ``params_rejected``."""
+        if not (isinstance(theta, torch.Tensor) and theta.is_cuda):
+            raise ValueError("theta must be a CUDA tensor")
+        if tuple(theta.shape) != (self.n, 4):
+            raise ValueError("theta must have shape (n, 4)")
+        with self._on_stream(inputs=[theta]):
+            t = theta.detach().to(torch.float32).contiguous()
+            self._check(self._lib.sim_set_params_device(self._h, _ptr(t)))
+
+    def params_rejected(self) -> int:
+        """Rows ``set_params_device`` rejected since the last call (waits for
+        the handle's stream)."""
+        out = ctypes.c_int32(0)
+        self._check(self._lib.sim_params_rejected(self._h, ctypes.byref(out)))
+        return int(out.value)
+
     def reset(self, seeds: Optional[Sequence[int]] = None):
         arr = None
         if seeds is not None:

@@ -113,6 +113,8 @@ def test_null_handle_calls_are_rejected(lib):
     assert lib.sim_run(None, 1) == _abi.SIM_E_ARG
     assert lib.sim_get_state(None, 0, None) == _abi.SIM_E_ARG
     assert lib.sim_adjoint(None, None, None) == _abi.SIM_E_ARG
+    assert lib.sim_set_params_device(None, None) == _abi.SIM_E_ARG
+    assert lib.sim_params_rejected(None, None) == _abi.SIM_E_ARG
     lib.sim_destroy(None)
 
 

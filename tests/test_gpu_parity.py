@@ -1087,6 +1087,63 @@ def test_gradient_steps_with_new_parameters_and_seeds(Sim, shape):
         assert np.all(np.abs(gb - go) <= 1e-4 * np.abs(go) + 1e-6 * scale), (gb, go)
 
 
+def test_parameters_from_device_memory(Sim):
+    """sim_set_params_device (Algorithm 1's theta from device memory, p_continue
+    kept) gives the gradient steps of sim_set_params bit for bit; invalid
+    rows keep their parameters and are counted; parameters set on the device
+    survive a change of tile shape (the host copies are refreshed before the
+    jobs are uploaded again)."""
+    import torch
+    T = 30
+    scs, ys = zip(*[calib_case(70, 90, 31 + b, T) for b in range(2)])
+    y = np.concatenate([t.ravel() for t in ys])
+    host = Sim(list(scs), calib=True, T_max=T, ckpt_every=10)
+    dev = Sim(list(scs), calib=True, T_max=T, ckpt_every=10)
+    for th, sd in [((0.55, 0.04, 0.05, 0.12), 3), ((0.62, 0.05, 0.07, 0.09), 4)]:
+        seeds = [sd * 100 + b for b in range(len(scs))]
+        host.set_params([th + (sc.p_continue,) for sc in scs])
+        host.reset(seeds)
+        host.run(T)
+        Lh, gh = host.loss_grad(y, 0)
+        dev.set_params_device(torch.tensor([th] * len(scs), device="cuda"))
+        dev.reset(seeds)
+        dev.run(T)
+        Ld, gd = dev.loss_grad(y, 0)
+        assert np.array_equal(Lh.cpu().numpy(), Ld.cpu().numpy()), th
+        assert np.array_equal(gh.cpu().numpy(), gd.cpu().numpy()), th
+    assert dev.params_rejected() == 0
+    # rows with a NaN or p_h < 0 are rejected: scenario 0 keeps th, 1 takes th2
+    th2 = (0.5, 0.05, 0.06, 0.1)
+    bad = torch.tensor([[float("nan"), 0.05, 0.06, 0.1], th2], device="cuda")
+    dev.set_params_device(bad)
+    dev.set_params_device(torch.tensor([[-0.1, 0.05, 0.06, 0.1], th2], device="cuda"))
+    assert dev.params_rejected() == 2
+    assert dev.params_rejected() == 0
+    dev.reset([7, 8])
+    dev.run(T)
+    Ld, gd = dev.loss_grad(y, 0)
+    ref = Sim([scs[0].with_params(*th), scs[1].with_params(*th2)], calib=True, T_max=T,
+              ckpt_every=10)
+    ref.reset([7, 8])
+    ref.run(T)
+    Lr, gr = ref.loss_grad(y, 0)
+    assert np.array_equal(Ld.cpu().numpy(), Lr.cpu().numpy())
+    assert np.array_equal(gd.cpu().numpy(), gr.cpu().numpy())
+    # a new tile shape uploads the jobs again: the device parameters stay
+    ex = dict(tile_rows=32, tile_words=4, depth=8, skip=3, threads=256)
+    dev.set_exec(**ex)
+    ref.set_exec(**ex)
+    for sim in (dev, ref):
+        sim.reset([9, 10])
+        sim.run(T)
+    Ld, gd = dev.loss_grad(y, 0)
+    Lr, gr = ref.loss_grad(y, 0)
+    assert np.array_equal(Ld.cpu().numpy(), Lr.cpu().numpy())
+    assert np.array_equal(gd.cpu().numpy(), gr.cpu().numpy())
+    with pytest.raises(ValueError):
+        dev.set_params_device(torch.zeros(3, 4, device="cuda"))
+
+
 def test_non_default_stream(Sim):
     """A handle on its own stream, called from code running on another
     stream, gives the same results as one on the current stream."""
