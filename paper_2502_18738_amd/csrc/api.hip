@@ -389,9 +389,15 @@ int refresh_worklist(sim_handle* h, bool dup) {
 // parameters and wind (every reset starts from the same burning cells, so
 // the region and every entry are those it would rebuild).
 int take_origin(sim_handle* h, int origin_step, bool reset) {
-    if (!(reset && h->q_reset && !h->q_params && !h->q_dirty)) h->q_dirty = true;
+    const bool keep = reset && h->q_reset && !h->q_params && !h->q_dirty;
+    if (!keep) h->q_dirty = true;
     h->q_reset = reset;
     h->q_origin = origin_step;
+    // a kept table needs no new burning box: the box and block bits of the
+    // reset state it was built from are still in place (only this function
+    // writes them, and the previous call was a reset as well), and a longer
+    // run that grows the table reads them again
+    if (keep) return SIM_OK;
     return h->hip(fs::launch_bbox(h->st, h->d_jobs(), h->n, h->parity, h->max_words, h->d_fbox(),
                                   reinterpret_cast<uint32_t*>(h->ws + h->L.qbits), h->L.qwords),
                   "burning box");
